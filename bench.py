@@ -1,0 +1,213 @@
+"""Benchmark: interlaced light-field frames/s on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--cluster-size 8]
+                    [--no-cpu-baseline] [--no-plain] [--workload outdoor]
+
+Workload (default ``outdoor``): 3,000,000 Gaussians (64-cluster mixture plus a
+far shell, SH degree 3), 100 views over 50 degrees, 3840x2160 panel, slant
+1/5, pitch 31/5; rendered with cross-view reuse (cluster size 8) and the
+view-coherent remapped blend.  A step is one interlaced frame: projection,
+key generation, sorting, ranges and blending, with the scene and cameras
+already resident.  The plain baseline renders every view at full resolution
+and interlaces.  One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "interlaced LF frames/s (4K, 100 views) reuse+remap vs plain; fwd+bwd ms"
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6: 256 CUs x 64 lanes x FMA x 2.4 GHz
+FLOPS_PER_EVAL = 14      # alpha: dx,dy (2) + w fma (2) + A'w, G'dy, *dy (3) + fma (2) + exp2 (1)
+                         #        + o*e (1) + min (1) + cutoff test (1)
+FLOPS_PER_BLEND = 6      # 1-a, T*(1-a), stop test, c*a, fma (2)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="outdoor")
+    ap.add_argument("--cluster-size", type=int, default=8)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=96)
+    return ap.parse_args()
+
+
+def timed(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, scene, cams, n_samples):
+    """The oracle, single-threaded, on a bounded sample of the same frame:
+    one projection of all Gaussians (timed alone) plus a blend of n_samples
+    subpixels of one view inside one cluster; extrapolated to a full frame as
+    (clusters + views) projections + 3WH subpixel blends."""
+    import numpy as np
+    import oracle
+    V = oracle.view_map(w.display)
+    S = 8
+    _, rep = oracle.cluster_table(w.display.num_views, S)
+    ref_views = np.unique(V)
+    j = int(ref_views[len(ref_views) // 2])
+    r = int(rep[j // S])
+    if j == r:
+        j = int(ref_views[len(ref_views) // 2 + 1])
+    t0 = time.perf_counter()
+    oracle.project(scene, cams[r], w.display.width, w.display.height)
+    t_proj = time.perf_counter() - t0
+    flat = V.reshape(-1)
+    idx = np.flatnonzero(flat == j)
+    samples = np.sort(np.random.default_rng(0).choice(idx, n_samples, replace=False))
+    t0 = time.perf_counter()
+    oracle.render_subpixels(scene, cams, w.display, V, S, samples)
+    t_call = time.perf_counter() - t0
+    t_sub = max(t_call - 2 * t_proj, 1e-9) / n_samples
+    n_proj = len(ref_views) + len({int(rep[v // S]) for v in ref_views})
+    frame_s = n_proj * t_proj + flat.size * t_sub
+    return {
+        "value": 1.0 / frame_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
+        "sample": (f"1 projection of all {scene.num_gaussians} Gaussians ({t_proj:.2f} s) + {n_samples} subpixels of "
+                   f"view {j} at cluster size {S} ({t_call:.2f} s incl. 2 projections); extrapolated to "
+                   f"{n_proj} projections + {flat.size} subpixels per frame"),
+        "host": platform.processor() or platform.machine(),
+        "host_cores_available": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it would "
+              "shard); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2605_04509_amd import lfr
+    from workloads import get_workload
+    from workloads.cameras import pack_cameras
+
+    w = get_workload(args.workload)
+    log("generating", w.name)
+    scene = w.make_scene()
+    cams_np = pack_cameras(w.cameras())
+    cams = lfr.cameras_array(cams_np)
+    ctx = lfr.Context(0)
+    disp = lfr.Display(ctx, w.display)
+    ds = lfr.DeviceScene.from_numpy(scene, device="cuda:0")
+    out = torch.empty((w.display.height, w.display.width, 3), dtype=torch.float32, device="cuda:0")
+    sync = torch.cuda.synchronize
+    S = args.cluster_size
+
+    def frame(cs=S, remap=True, timing=False):
+        lfr.render(ctx, disp, ds, cams, cluster_size=cs, remap=remap, timing=timing, out=out)
+
+    # work counts of the blend (separate counting launch, outside any timed region)
+    frame()
+    lfr.render(ctx, disp, ds, cams, cluster_size=S, remap=True, out=out, count_work=True)
+    work = ctx.stats()
+    log("work", work)
+
+    for _ in range(args.warmup):
+        frame(timing=True)
+    sync()
+    # timed region: K frames; per-stage HIP events on the library's stream
+    stages = {k: 0.0 for k in ("ms_project", "ms_depth_sort", "ms_keygen", "ms_sort", "ms_ranges", "ms_blend")}
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        frame(timing=True)
+        st = ctx.stats()
+        for k in stages:
+            stages[k] += st[k]
+    sync()
+    sec = (time.perf_counter() - t0) / args.steps
+    stages = {k: v / args.steps for k, v in stages.items()}
+    fps = 1.0 / sec
+    log(f"reuse+remap S={S}: {sec * 1e3:.3f} ms/frame, {fps:.1f} frames/s, stages {stages}")
+
+    flops = FLOPS_PER_EVAL * work["evals"] + FLOPS_PER_BLEND * work["blended"]
+    achieved = flops / (stages["ms_blend"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "blend_remap_kernel", "achieved": achieved,
+                "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS, "traffic": None,
+                "evals": work["evals"], "blended": work["blended"], "launch_ms": stages["ms_blend"]}
+
+    result = {
+        "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{w.name}: {scene.num_gaussians} Gaussians (SH{scene.sh_degree}), "
+                                f"{w.display.num_views} views over {w.span_deg:g} deg, "
+                                f"{w.display.width}x{w.display.height}, slant {w.display.tan_slant.num}/"
+                                f"{w.display.tan_slant.den}, pitch {w.display.pitch.num}/{w.display.pitch.den}, "
+                                f"tile {w.display.tile_w}x{w.display.tile_h}"),
+                   "cluster_size": S, "remap": True, "parallelism": "single GPU"},
+        "stages_ms": stages, "pairs": work["pairs"], "clusters": work["clusters"], "views": work["views"],
+        "roofline": roofline, "fwd_bwd_ms": None,
+    }
+
+    if not args.no_ablation:
+        modes = {}
+        for name, cs, rm in (("reuse_only", S, False), ("remap_only", 1, True), ("neither", 1, False)):
+            frame(cs, rm)
+            t = timed(lambda: frame(cs, rm), 3, sync)
+            modes[name] = {"cluster_size": cs, "remap": rm, "frames_per_s": 1.0 / t, "ms": t * 1e3}
+            log(name, modes[name])
+        modes["reuse+remap"] = {"cluster_size": S, "remap": True, "frames_per_s": fps, "ms": sec * 1e3}
+        result["modes"] = modes
+
+    if not args.no_plain:
+        plain = {}
+        for label, cull in (("all_views", False), ("referenced_views", True)):
+            best = None
+            for vb in (10, 25, 50):
+                def pf(vb=vb, cull=cull):
+                    lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out)
+                pf()
+                t = timed(pf, 1, sync)
+                log(f"plain {label} batch {vb}: {t * 1e3:.1f} ms")
+                if best is None or t < best[1]:
+                    best = (vb, t)
+            vb = best[0]
+            t = timed(lambda: lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out),
+                      args.plain_steps, sync)
+            plain[label] = {"view_batch": vb, "frames_per_s": 1.0 / t, "ms": t * 1e3}
+        result["plain"] = plain
+        result["speedup_vs_plain"] = fps / plain["all_views"]["frames_per_s"]
+        result["speedup_vs_plain_referenced"] = fps / plain["referenced_views"]["frames_per_s"]
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(w, scene, cams_np, args.cpu_samples)
+
+    disp.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

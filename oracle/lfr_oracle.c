@@ -33,8 +33,8 @@
 #define NEAR_Z    0.2f              /* near plane on the float32 depth      */
 #define DILATION  0.3               /* added to the 2D covariance diagonal  */
 #define CLAMP_FOV 1.3               /* Jacobian clamp, in units of tan(fov/2) */
-#define FLAG_ALPHA_REL 1e-5
-#define FLAG_T_REL     1e-3
+#define U32 5.9604644775390625e-08  /* float32 unit roundoff 2^-24 */
+#define FLAG_SAFETY 4.0
 
 /* ------------------------------------------------------------------------ */
 /* Eq. 1-3                                                                  */
@@ -358,29 +358,45 @@ static void blend(double px, double py, int u0, int u1, const int64_t *order, in
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     int32_t flag = 0;
     double tflag = 0.0;
+    double relT = 0.0;   /* bound on the relative error of a float32 T so far */
     for (int64_t e = 0; e < n; ++e) {
         int64_t i = order[e];
         const orc_proj *g = rep + i, *m = view + i;
         if (!m->valid_mean) continue;
         double dx = px - (double)m->mean2d[0];
         double dy = py - (double)m->mean2d[1];
-        double w = dx + (double)g->conic[1] * dy;
+        double beta = (double)g->conic[1];
+        double w = dx + beta * dy;
         double E = (double)g->conic[0] * w * w + (double)g->conic[2] * dy * dy;
         double alpha = (double)g->opacity * exp2(-E);
-        if (alpha > ALPHA_MAX) alpha = ALPHA_MAX;
-        if (fabs(alpha - 1.0 / 255.0) <= FLAG_ALPHA_REL * (1.0 / 255.0)) {
+        int clamped = alpha > ALPHA_MAX;
+        if (clamped) alpha = ALPHA_MAX;
+        /* Near-threshold detection.  A float32 evaluation of the same
+         * formulas (dx, dy, w = dx + beta dy, A' w^2 + G' dy^2, exp2 within one
+         * ulp, the opacity product) has, to first order in the unit roundoff
+         * u, an error in E of at most u * SE and a relative error in alpha of
+         * at most ea = ln2 * u * SE + 3u; T carries the accumulated bound
+         * relT.  An alpha or T' within FLAG_SAFETY times its bound of a
+         * threshold may fall on the other side in float32: such subpixels are
+         * flagged. */
+        double SE = 2.0 * (double)g->conic[0] * fabs(w) * (fabs(dx) + fabs(beta * dy) + fabs(w))
+                  + (double)g->conic[0] * w * w + 4.0 * (double)g->conic[2] * dy * dy + E;
+        double ea = clamped ? 1e-6 : 0.6931471805599453 * U32 * SE + 3.0 * U32;
+        if (fabs(alpha - 1.0 / 255.0) <= FLAG_SAFETY * ea * alpha) {
             if (!flag) tflag = T;
             flag |= 1;
         }
         if ((float)alpha < ALPHA_MIN) continue;
         double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - 1e-4) <= FLAG_T_REL * 1e-4) {
+        double step = (clamped ? 1e-6 : alpha / (1.0 - alpha) * ea) + 2.0 * U32;
+        if (fabs(Tn - 1e-4) <= FLAG_SAFETY * (relT + step) * Tn) {
             if (!flag) tflag = T;
             flag |= 2;
         }
         if ((float)Tn < T_STOP) break;
         for (int u = u0; u < u1; ++u) C[u] = C[u] + (double)g->color[u] * alpha * T;
         T = Tn;
+        relT += step;
     }
     for (int u = u0; u < u1; ++u) out[u - u0] = (float)(C[u] + T * (double)bg[u]);
     if (flag_out) *flag_out = flag;

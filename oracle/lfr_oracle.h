@@ -70,8 +70,10 @@ void orc_sh_basis(int32_t degree, const double dir[3], double *out);
  * (S = 1 is the exact subpixel path).  samples are panel-linear indices.
  * cams: [N][16].  V: the full [H][W][3] view map.  For every sample:
  *   out    the rendered value (C + T * bg),
- *   flags  bit 0: some alpha was within 1e-5 (relative) of 1/255,
- *          bit 1: some T' was within 1e-3 (relative) of 1e-4,
+ *   flags  bit 0: some alpha was within the float32 error bound of 1/255,
+ *          bit 1: some T' was within the float32 error bound of 1e-4
+ *          (bounds: a first-order error analysis of the float32 evaluation
+ *          of Eq. 10 and of the transmittance product, times 4),
  *   tflag  the transmittance T just before the first flagged event (0 if none).
  * Returns 0, or -1 for invalid arguments. */
 int orc_render_subpixels(int64_t M, int32_t sh_degree, const float *means,

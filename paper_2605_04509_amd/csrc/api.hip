@@ -1,0 +1,959 @@
+// C ABI of liblfr: argument validation, workspace management and the stage
+// sequence of the renderer (appendix B.2 algorithm), all enqueued on the
+// context's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "lfr_internal.h"
+
+using namespace lfr;
+
+namespace {
+
+enum Slot {
+    kRec, kExt, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
+    kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
+    kWork, kNumSlots
+};
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct lfr_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t limit = 0;
+    std::string err;
+    lfr_stats stats{};
+    Buf ws[kNumSlots];
+    void *pinned = nullptr;
+    size_t pinned_n = 0;
+    hipEvent_t ev[8] = {};
+    bool events = false;
+};
+
+struct lfr_display {
+    int device = 0;
+    int W = 0, H = 0, N = 0, tw = 0, th = 0, TX = 0, TY = 0, T = 0;
+    uint16_t *d_V = nullptr;
+    uint32_t *d_psi = nullptr;
+    std::vector<uint8_t> ref;  // referenced-view mask
+    int n_ref = 0;
+    std::map<int64_t, TaskSet> tasks;
+};
+
+namespace {
+
+lfr_status fail(lfr_context *ctx, lfr_status code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), LFR_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                       \
+    } while (0)
+
+#define CHK(expr)                    \
+    do {                             \
+        lfr_status s_ = (expr);      \
+        if (s_ != LFR_OK) return s_; \
+    } while (0)
+
+uint64_t ws_total(const lfr_context *ctx)
+{
+    uint64_t t = 0;
+    for (const Buf &b : ctx->ws) t += b.n;
+    return t;
+}
+
+// Grow-only workspace slot.
+lfr_status ws_get(lfr_context *ctx, Slot s, size_t bytes, void **out)
+{
+    Buf &b = ctx->ws[s];
+    if (bytes == 0) bytes = 1;
+    if (b.n < bytes) {
+        size_t want = bytes + bytes / 8 + 256;
+        const uint64_t after = ws_total(ctx) - b.n + want;
+        if (ctx->limit && after > ctx->limit) {
+            want = bytes;
+            if (ws_total(ctx) - b.n + want > ctx->limit)
+                return fail(ctx, LFR_ERR_CAPACITY, "workspace limit %llu bytes exceeded (need %llu)",
+                            (unsigned long long)ctx->limit, (unsigned long long)(ws_total(ctx) - b.n + want));
+        }
+        if (b.p) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            HIPCHK(ctx, hipFree(b.p));
+            b.p = nullptr;
+            b.n = 0;
+        }
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(ctx, LFR_ERR_OUT_OF_MEMORY, "hipMalloc of %llu bytes failed", (unsigned long long)want);
+        }
+        b.n = want;
+    }
+    *out = b.p;
+    return LFR_OK;
+}
+
+template <typename T>
+lfr_status ws_get_t(lfr_context *ctx, Slot s, size_t count, T **out)
+{
+    void *p = nullptr;
+    CHK(ws_get(ctx, s, count * sizeof(T), &p));
+    *out = (T *)p;
+    return LFR_OK;
+}
+
+lfr_status pinned_get(lfr_context *ctx, size_t bytes, void **out)
+{
+    if (ctx->pinned_n < bytes) {
+        if (ctx->pinned) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            HIPCHK(ctx, hipHostFree(ctx->pinned));
+            ctx->pinned = nullptr;
+            ctx->pinned_n = 0;
+        }
+        const size_t want = std::max<size_t>(bytes, 1 << 16);
+        HIPCHK(ctx, hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+        ctx->pinned_n = want;
+    }
+    *out = ctx->pinned;
+    return LFR_OK;
+}
+
+int bits_for(int64_t n)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+bool cam_ok(const lfr_camera &c)
+{
+    for (float v : c.R)
+        if (!isfinite(v)) return false;
+    for (float v : c.t)
+        if (!isfinite(v)) return false;
+    return isfinite(c.fx) && isfinite(c.fy) && isfinite(c.cx) && isfinite(c.cy) && c.fx > 0 && c.fy > 0;
+}
+
+DevCamera dev_camera(const lfr_camera &c, int W, int H)
+{
+    DevCamera d;
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    d.limx = kClampFov * ((0.5 * (double)W) / d.fx);
+    d.limy = kClampFov * ((0.5 * (double)H) / d.fy);
+    for (int a = 0; a < 3; ++a)
+        d.campos[a] = -((d.R[0 + a] * d.t[0] + d.R[3 + a] * d.t[1]) + d.R[6 + a] * d.t[2]);
+    return d;
+}
+
+lfr_status check_scene(lfr_context *ctx, const lfr_scene *sc)
+{
+    if (!sc) return fail(ctx, LFR_ERR_INVALID_ARG, "scene is NULL");
+    if (sc->num_gaussians < 0 || sc->num_gaussians > (int64_t)0x7FFFFFFF)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "num_gaussians %lld out of range", (long long)sc->num_gaussians);
+    if (sc->sh_degree < 0 || sc->sh_degree > 3)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "sh_degree %d not in [0,3]", sc->sh_degree);
+    if (sc->num_gaussians > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacities || !sc->sh))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "scene array pointer is NULL");
+    return LFR_OK;
+}
+
+SceneDev scene_dev(const lfr_scene *sc)
+{
+    return SceneDev{sc->num_gaussians, sc->sh_degree, sc->means, sc->log_scales, sc->quats, sc->opacities, sc->sh};
+}
+
+// Host tables of compact clusters / view slots for cluster size S.
+ViewTables build_tables(const lfr_display *d, int S, bool cull)
+{
+    ViewTables vt;
+    const int N = d->N;
+    const int K = (N + S - 1) / S;
+    vt.view_slot.assign(N, -1);
+    vt.view_cluster.assign(N, -1);
+    std::vector<int> slot_of(N, -1);
+    // view slots: referenced views (cull) or all views
+    for (int j = 0; j < N; ++j)
+        if (!cull || d->ref[j]) {
+            slot_of[j] = (int)vt.view_ids.size();
+            vt.view_ids.push_back(j);
+        }
+    vt.cv_off.push_back(0);
+    for (int k = 0; k < K; ++k) {
+        std::vector<int> members;
+        for (int l = 0; l < S; ++l) {
+            const int j = std::min(k * S + l, N - 1);
+            if (std::find(members.begin(), members.end(), j) == members.end()) members.push_back(j);
+        }
+        std::vector<int> used;
+        for (int j : members)
+            if (slot_of[j] >= 0) used.push_back(j);
+        if (used.empty()) continue;
+        const int c = (int)vt.cluster_rep.size();
+        vt.cluster_rep.push_back(std::min(k * S + S / 2, N - 1));
+        for (int j : used) vt.cv_list.push_back(slot_of[j]);
+        vt.cv_off.push_back((int)vt.cv_list.size());
+        for (int j : members) vt.view_cluster[j] = c;
+    }
+    for (int j = 0; j < N; ++j) vt.view_slot[j] = slot_of[j];
+    vt.n_clusters = (int)vt.cluster_rep.size();
+    vt.n_views = (int)vt.view_ids.size();
+    return vt;
+}
+
+// Device copy of the small per-render tables, laid out in one buffer.
+struct DevTables {
+    DevCamera *cams = nullptr;
+    int32_t *cluster_cam = nullptr, *view_cam = nullptr, *cv_off = nullptr, *cv_list = nullptr,
+            *view_slot = nullptr, *view_cluster = nullptr;
+};
+
+lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camera *cams, const ViewTables &vt,
+                         DevTables *out)
+{
+    const int N = d->N;
+    const size_t cam_bytes = sizeof(DevCamera) * N;
+    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + vt.cv_list.size() + 2 * N;
+    const size_t bytes = cam_bytes + n_int * sizeof(int32_t) + 64;
+    void *h = nullptr, *dv = nullptr;
+    CHK(pinned_get(ctx, bytes, &h));
+    CHK(ws_get(ctx, kTables, bytes, &dv));
+    DevCamera *hc = (DevCamera *)h;
+    for (int j = 0; j < N; ++j) hc[j] = dev_camera(cams[j], d->W, d->H);
+    int32_t *hi = (int32_t *)((char *)h + cam_bytes);
+    int32_t *di = (int32_t *)((char *)dv + cam_bytes);
+    size_t o = 0;
+    auto put = [&](const std::vector<int32_t> &v, int32_t **dst) {
+        if (!v.empty()) memcpy(hi + o, v.data(), v.size() * sizeof(int32_t));
+        *dst = di + o;
+        o += v.size();
+    };
+    put(vt.cluster_rep, &out->cluster_cam);
+    put(vt.view_ids, &out->view_cam);
+    put(vt.cv_off, &out->cv_off);
+    put(vt.cv_list, &out->cv_list);
+    put(vt.view_slot, &out->view_slot);
+    put(vt.view_cluster, &out->view_cluster);
+    out->cams = (DevCamera *)dv;
+    HIPCHK(ctx, hipMemcpyAsync(dv, h, cam_bytes + o * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    return LFR_OK;
+}
+
+void record(lfr_context *ctx, int k, bool timing)
+{
+    if (timing) (void)hipEventRecord(ctx->ev[k], ctx->stream);
+}
+
+float elapsed(lfr_context *ctx, int a, int b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+lfr_status read_total(lfr_context *ctx, const uint64_t *d_total, uint64_t *host)
+{
+    void *h = nullptr;
+    CHK(pinned_get(ctx, 64, &h));
+    HIPCHK(ctx, hipMemcpyAsync(h, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *host = *(uint64_t *)h;
+    return LFR_OK;
+}
+
+// Project -> count -> depth sort -> scan -> emit -> tile sort -> ranges.
+// On success the sorted pair values and the ranges are in the outputs.
+struct Binned {
+    uint64_t P = 0;
+    uint32_t *vals = nullptr;
+    uint2 *ranges = nullptr;
+    GaussRec *rec = nullptr;
+    float2 *mean2d = nullptr;
+    int cluster_bits = 0;
+};
+
+lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_scene *scene, const DevTables &dt,
+                           const ViewTables &vt, bool timing, Binned *out)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t M = scene->num_gaussians;
+    const int KC = vt.n_clusters, NV = vt.n_views;
+    const int64_t MK = M * KC;
+    const int cbits = bits_for(KC);
+    const int tbits = bits_for(d->T);
+    if (cbits + tbits > 32)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "tile (%d bits) + cluster (%d bits) keys exceed 32 bits", tbits, cbits);
+    if (MK > (int64_t)0xFFFFFFFFll)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "Gaussians x clusters = %lld exceeds 2^32", (long long)MK);
+
+    ProjectOut po;
+    uint32_t *counts, *counts_sorted, *offsets;
+    uint64_t *dkey1, *d_total;
+    uint32_t *dval1;
+    void *scan_temp, *sort_temp;
+    CHK(ws_get_t(ctx, kRec, MK, &po.rec));
+    CHK(ws_get_t(ctx, kExt, MK, &po.ext));
+    CHK(ws_get_t(ctx, kDKey0, MK, &po.dkey));
+    CHK(ws_get_t(ctx, kDVal0, MK, &po.dval));
+    CHK(ws_get_t(ctx, kDKey1, MK, &dkey1));
+    CHK(ws_get_t(ctx, kDVal1, MK, &dval1));
+    CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
+    CHK(ws_get_t(ctx, kCounts, MK, &counts));
+    CHK(ws_get_t(ctx, kCountsSorted, MK, &counts_sorted));
+    CHK(ws_get_t(ctx, kOffsets, MK, &offsets));
+    CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(MK), &scan_temp));
+    CHK(ws_get_t(ctx, kTotal, 8, &d_total));
+
+    record(ctx, 1, timing);
+    HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, d->W, d->H, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
+    record(ctx, 2, timing);
+
+    BinParams bp;
+    bp.M = M;
+    bp.n_clusters = KC;
+    bp.W = d->W;
+    bp.H = d->H;
+    bp.tw = d->tw;
+    bp.th = d->th;
+    bp.TX = d->TX;
+    bp.TY = d->TY;
+    bp.cluster_bits = cbits;
+    bp.cv_off = dt.cv_off;
+    bp.cv_list = dt.cv_list;
+    HIPCHK(ctx, launch_tile_count(bp, po.mean2d, po.ext, po.dkey, counts, s));
+
+    // per-cluster depth order: sort (cluster << 32 | depth bits, i)
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MK), &sort_temp));
+    bool alt = false;
+    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MK, 0, 32 + cbits, sort_temp, &alt, s));
+    const uint64_t *dks = alt ? dkey1 : po.dkey;
+    const uint32_t *dvs = alt ? dval1 : po.dval;
+    record(ctx, 3, timing);
+    HIPCHK(ctx, launch_gather_counts(dks, dvs, M, MK, counts, counts_sorted, s));
+    HIPCHK(ctx, launch_exclusive_scan(counts_sorted, offsets, MK, scan_temp, d_total, s));
+    uint64_t P = 0;
+    CHK(read_total(ctx, d_total, &P));
+    if (P >= 0xFFFFFFFFull)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "%llu Gaussian-tile pairs exceed 2^32", (unsigned long long)P);
+
+    uint32_t *pk0, *pv0, *pk1, *pv1;
+    CHK(ws_get_t(ctx, kPairK0, P, &pk0));
+    CHK(ws_get_t(ctx, kPairV0, P, &pv0));
+    CHK(ws_get_t(ctx, kPairK1, P, &pk1));
+    CHK(ws_get_t(ctx, kPairV1, P, &pv1));
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)MK)), &sort_temp));
+    HIPCHK(ctx, launch_tile_emit(bp, po.mean2d, po.ext, dks, dvs, offsets, counts_sorted, pk0, pv0, s));
+    record(ctx, 4, timing);
+    bool palt = false;
+    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, cbits, cbits + tbits, sort_temp, &palt, s));
+    const uint32_t *keys = palt ? pk1 : pk0;
+    record(ctx, 5, timing);
+    const int64_t n_ranges = (int64_t)d->T << cbits;
+    uint2 *ranges;
+    CHK(ws_get_t(ctx, kRanges, n_ranges, &ranges));
+    HIPCHK(ctx, launch_fill_u32((uint32_t *)ranges, 0u, 2 * n_ranges, s));
+    HIPCHK(ctx, launch_ranges(keys, (int64_t)P, ranges, s));
+    record(ctx, 6, timing);
+
+    out->P = P;
+    out->vals = palt ? pv1 : pv0;
+    out->ranges = ranges;
+    out->rec = po.rec;
+    out->mean2d = po.mean2d;
+    out->cluster_bits = cbits;
+    return LFR_OK;
+}
+
+lfr_status get_tasks(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
+{
+    const int64_t key = (int64_t)S * 2 + (cull ? 1 : 0);
+    auto it = d->tasks.find(key);
+    if (it != d->tasks.end()) {
+        *out = &it->second;
+        return LFR_OK;
+    }
+    hipStream_t s = ctx->stream;
+    TaskSet ts;
+    HIPCHK(ctx, hipMalloc(&ts.d_view_cluster, sizeof(int32_t) * d->N));
+    HIPCHK(ctx, hipMemcpy(ts.d_view_cluster, vt.view_cluster.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice));
+    uint32_t *cnt = nullptr, *off = nullptr;
+    uint64_t *tot = nullptr;
+    void *tmp = nullptr;
+    HIPCHK(ctx, hipMalloc(&cnt, sizeof(uint32_t) * d->T));
+    HIPCHK(ctx, hipMalloc(&off, sizeof(uint32_t) * d->T));
+    HIPCHK(ctx, hipMalloc(&tot, sizeof(uint64_t)));
+    HIPCHK(ctx, hipMalloc(&tmp, scan_temp_bytes(d->T)));
+    HIPCHK(ctx, launch_task_count(d->d_V, d->d_psi, ts.d_view_cluster, d->W, d->H, d->tw, d->th, cnt, s));
+    HIPCHK(ctx, launch_exclusive_scan(cnt, off, d->T, tmp, tot, s));
+    uint64_t n = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&n, tot, sizeof n, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    HIPCHK(ctx, hipMalloc(&ts.d_tasks, sizeof(Task) * std::max<uint64_t>(n, 1)));
+    HIPCHK(ctx, launch_task_emit(d->d_V, d->d_psi, ts.d_view_cluster, d->W, d->H, d->tw, d->th, off, ts.d_tasks, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    ts.n = (int)n;
+    (void)hipFree(cnt);
+    (void)hipFree(off);
+    (void)hipFree(tot);
+    (void)hipFree(tmp);
+    auto ins = d->tasks.emplace(key, ts);
+    *out = &ins.first->second;
+    return LFR_OK;
+}
+
+lfr_status begin(lfr_context *ctx)
+{
+    if (!ctx) return LFR_ERR_INVALID_ARG;
+    ctx->err.clear();
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return LFR_OK;
+}
+
+lfr_status check_render_args(lfr_context *ctx, const lfr_display *d, const lfr_scene *scene,
+                             const lfr_camera *cams, int32_t num_cams, const lfr_render_opts *opts, const float *out)
+{
+    if (!d) return fail(ctx, LFR_ERR_INVALID_ARG, "display is NULL");
+    if (d->device != ctx->device) return fail(ctx, LFR_ERR_INVALID_ARG, "display lives on another device");
+    CHK(check_scene(ctx, scene));
+    if (!cams) return fail(ctx, LFR_ERR_INVALID_ARG, "cameras are NULL");
+    if (num_cams != d->N) return fail(ctx, LFR_ERR_INVALID_ARG, "num_cams %d != num_views %d", num_cams, d->N);
+    for (int j = 0; j < num_cams; ++j)
+        if (!cam_ok(cams[j])) return fail(ctx, LFR_ERR_INVALID_ARG, "camera %d is not finite or has f <= 0", j);
+    if (!opts) return fail(ctx, LFR_ERR_INVALID_ARG, "opts is NULL");
+    if (opts->cluster_size < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "cluster_size must be >= 1");
+    if (opts->cluster_size > kMaxClusterViews)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "cluster_size %d > %d", opts->cluster_size, kMaxClusterViews);
+    for (float b : opts->background)
+        if (!isfinite(b)) return fail(ctx, LFR_ERR_INVALID_ARG, "background is not finite");
+    if (!out) return fail(ctx, LFR_ERR_INVALID_ARG, "output is NULL");
+    return LFR_OK;
+}
+
+lfr_status finish_timing(lfr_context *ctx, bool timing, int last)
+{
+    if (!timing) return LFR_OK;
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[last]));
+    ctx->stats.ms_project = elapsed(ctx, 1, 2);
+    ctx->stats.ms_depth_sort = elapsed(ctx, 2, 3);
+    ctx->stats.ms_keygen = elapsed(ctx, 3, 4);
+    ctx->stats.ms_sort = elapsed(ctx, 4, 5);
+    ctx->stats.ms_ranges = elapsed(ctx, 5, 6);
+    ctx->stats.ms_blend = elapsed(ctx, 6, 7);
+    ctx->stats.ms_total = elapsed(ctx, 0, 7);
+    return LFR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+lfr_status lfr_context_create(int32_t device, void *hip_stream, lfr_context **out)
+{
+    if (!out) return LFR_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return LFR_ERR_INVALID_ARG;
+    }
+    if (hipSetDevice(device) != hipSuccess) return LFR_ERR_HIP;
+    lfr_context *ctx = new lfr_context();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    for (auto &e : ctx->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            lfr_context_destroy(ctx);
+            return LFR_ERR_HIP;
+        }
+    *out = ctx;
+    return LFR_OK;
+}
+
+void lfr_context_destroy(lfr_context *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (Buf &b : ctx->ws)
+        if (b.p) (void)hipFree(b.p);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+lfr_status lfr_context_set_stream(lfr_context *ctx, void *hip_stream)
+{
+    if (!ctx) return LFR_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return LFR_OK;
+}
+
+lfr_status lfr_context_set_limit(lfr_context *ctx, uint64_t max_workspace_bytes)
+{
+    if (!ctx) return LFR_ERR_INVALID_ARG;
+    ctx->limit = max_workspace_bytes;
+    return LFR_OK;
+}
+
+lfr_status lfr_context_trim(lfr_context *ctx)
+{
+    CHK(begin(ctx));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (Buf &b : ctx->ws) {
+        if (b.p) HIPCHK(ctx, hipFree(b.p));
+        b.p = nullptr;
+        b.n = 0;
+    }
+    return LFR_OK;
+}
+
+lfr_status lfr_get_stats(const lfr_context *ctx, lfr_stats *out)
+{
+    if (!ctx || !out) return LFR_ERR_INVALID_ARG;
+    *out = ctx->stats;
+    out->workspace_bytes = ws_total(ctx);
+    return LFR_OK;
+}
+
+const char *lfr_last_error(const lfr_context *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+static lfr_status display_finish(lfr_context *ctx, lfr_display *d, lfr_display **out)
+{
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipMalloc(&d->d_psi, sizeof(uint32_t) * 3 * (size_t)d->W * d->H));
+    HIPCHK(ctx, launch_remap(d->d_V, d->W, d->H, d->tw, d->th, d->d_psi, s));
+    uint32_t *mask = nullptr;
+    HIPCHK(ctx, hipMalloc(&mask, sizeof(uint32_t) * d->N));
+    HIPCHK(ctx, launch_fill_u32(mask, 0u, d->N, s));
+    HIPCHK(ctx, launch_referenced_views(d->d_V, 3ll * d->W * d->H, mask, s));
+    std::vector<uint32_t> hm(d->N);
+    HIPCHK(ctx, hipMemcpyAsync(hm.data(), mask, sizeof(uint32_t) * d->N, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    (void)hipFree(mask);
+    d->ref.assign(d->N, 0);
+    d->n_ref = 0;
+    for (int j = 0; j < d->N; ++j)
+        if (hm[j]) {
+            d->ref[j] = 1;
+            ++d->n_ref;
+        }
+    *out = d;
+    return LFR_OK;
+}
+
+static bool tile_ok(int t) { return t == 8 || t == 16 || t == 32; }
+
+static lfr_display *new_display(lfr_context *ctx, int W, int H, int N, int tw, int th)
+{
+    lfr_display *d = new lfr_display();
+    d->device = ctx->device;
+    d->W = W;
+    d->H = H;
+    d->N = N;
+    d->tw = tw;
+    d->th = th;
+    d->TX = (W + tw - 1) / tw;
+    d->TY = (H + th - 1) / th;
+    d->T = d->TX * d->TY;
+    return d;
+}
+
+lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lfr_display **out)
+{
+    CHK(begin(ctx));
+    if (!desc || !out) return fail(ctx, LFR_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    const lfr_display_desc &D = *desc;
+    if (D.width < 1 || D.height < 1 || (int64_t)D.width * D.height > (int64_t)1 << 30)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "panel %d x %d out of range", D.width, D.height);
+    if (D.num_views < 1 || D.num_views > 65535)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "num_views %d not in [1, 65535]", D.num_views);
+    if (D.tan_slant.den <= 0 || D.pitch.den <= 0 || D.offset.den <= 0 || D.pitch.num <= 0)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "rational parameters need den > 0 and pitch > 0");
+    if (!tile_ok(D.tile_w) || !tile_ok(D.tile_h))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: each side must be 8, 16 or 32", D.tile_w, D.tile_h);
+    // Exact-integer form of Eq. 1-3; every intermediate must fit in int64.
+    typedef __int128 i128;
+    auto g = [](i128 a, i128 b) {
+        if (a < 0) a = -a;
+        if (b < 0) b = -b;
+        while (b) {
+            i128 t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    };
+    i128 Q = D.tan_slant.den;
+    Q = Q / g(Q, D.pitch.den) * D.pitch.den;
+    Q = Q / g(Q, D.offset.den) * D.offset.den;
+    const i128 lim = (i128)1 << 62;
+    const i128 qa = Q, qb = Q * 3 * D.tan_slant.num / D.tan_slant.den, qc = (i128)D.offset.num * (Q / D.offset.den),
+               P = (i128)D.pitch.num * (Q / D.pitch.den);
+    const i128 absq = qb < 0 ? -qb : qb, absc = qc < 0 ? -qc : qc;
+    const i128 maxD = (i128)3 * D.width * qa + (i128)D.height * absq + absc;
+    if (Q > lim || maxD > lim || P > lim || P * D.num_views > lim)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "lens parameters too large for 64-bit exact arithmetic");
+    lfr_display *d = new_display(ctx, D.width, D.height, D.num_views, D.tile_w, D.tile_h);
+    ViewMapParams vp{D.width, D.height, D.num_views, (int64_t)qa, (int64_t)qb, (int64_t)qc, (int64_t)P};
+    lfr_status st = LFR_OK;
+    if (hipMalloc(&d->d_V, sizeof(uint16_t) * 3 * (size_t)D.width * D.height) != hipSuccess) {
+        st = fail(ctx, LFR_ERR_OUT_OF_MEMORY, "hipMalloc for the view map failed");
+    } else if (launch_view_map(vp, d->d_V, ctx->stream) != hipSuccess) {
+        st = fail(ctx, LFR_ERR_HIP, "view map launch failed");
+    } else {
+        st = display_finish(ctx, d, out);
+    }
+    if (st != LFR_OK) lfr_display_destroy(d);
+    return st;
+}
+
+lfr_status lfr_display_create_from_map(lfr_context *ctx, int32_t W, int32_t H, int32_t N, const int32_t *view_map,
+                                       int32_t tw, int32_t th, lfr_display **out)
+{
+    CHK(begin(ctx));
+    if (!view_map || !out) return fail(ctx, LFR_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || N < 1 || N > 65535)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "bad panel or view count");
+    if (!tile_ok(tw) || !tile_ok(th)) return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+    const size_t n = 3 * (size_t)W * H;
+    std::vector<uint16_t> v16(n);
+    for (size_t s = 0; s < n; ++s) {
+        if (view_map[s] < 0 || view_map[s] >= N)
+            return fail(ctx, LFR_ERR_INVALID_ARG, "view_map[%zu] = %d not in [0, %d)", s, view_map[s], N);
+        v16[s] = (uint16_t)view_map[s];
+    }
+    lfr_display *d = new_display(ctx, W, H, N, tw, th);
+    lfr_status st = LFR_OK;
+    if (hipMalloc(&d->d_V, sizeof(uint16_t) * n) != hipSuccess) {
+        st = fail(ctx, LFR_ERR_OUT_OF_MEMORY, "hipMalloc for the view map failed");
+    } else if (hipMemcpy(d->d_V, v16.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice) != hipSuccess) {
+        st = fail(ctx, LFR_ERR_HIP, "view map upload failed");
+    } else {
+        st = display_finish(ctx, d, out);
+    }
+    if (st != LFR_OK) lfr_display_destroy(d);
+    return st;
+}
+
+void lfr_display_destroy(lfr_display *d)
+{
+    if (!d) return;
+    (void)hipSetDevice(d->device);
+    (void)hipDeviceSynchronize();
+    if (d->d_V) (void)hipFree(d->d_V);
+    if (d->d_psi) (void)hipFree(d->d_psi);
+    for (auto &kv : d->tasks) {
+        if (kv.second.d_tasks) (void)hipFree(kv.second.d_tasks);
+        if (kv.second.d_view_cluster) (void)hipFree(kv.second.d_view_cluster);
+    }
+    delete d;
+}
+
+lfr_status lfr_display_get_view_map(const lfr_display *d, int32_t *host_out)
+{
+    if (!d || !host_out) return LFR_ERR_INVALID_ARG;
+    if (hipSetDevice(d->device) != hipSuccess) return LFR_ERR_HIP;
+    const size_t n = 3 * (size_t)d->W * d->H;
+    std::vector<uint16_t> v(n);
+    if (hipDeviceSynchronize() != hipSuccess) return LFR_ERR_HIP;
+    if (hipMemcpy(v.data(), d->d_V, n * sizeof(uint16_t), hipMemcpyDeviceToHost) != hipSuccess) return LFR_ERR_HIP;
+    for (size_t s = 0; s < n; ++s) host_out[s] = v[s];
+    return LFR_OK;
+}
+
+lfr_status lfr_display_get_remap(const lfr_display *d, uint32_t *host_out)
+{
+    if (!d || !host_out) return LFR_ERR_INVALID_ARG;
+    if (hipSetDevice(d->device) != hipSuccess) return LFR_ERR_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return LFR_ERR_HIP;
+    const size_t n = 3 * (size_t)d->W * d->H;
+    if (hipMemcpy(host_out, d->d_psi, n * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return LFR_ERR_HIP;
+    return LFR_OK;
+}
+
+lfr_status lfr_display_referenced_views(const lfr_display *d, int32_t *count, uint8_t *host_mask)
+{
+    if (!d) return LFR_ERR_INVALID_ARG;
+    if (count) *count = d->n_ref;
+    if (host_mask) memcpy(host_mask, d->ref.data(), d->N);
+    return LFR_OK;
+}
+
+lfr_status lfr_make_view_cone(const lfr_view_cone *c, lfr_camera *out)
+{
+    if (!c || !out || c->num_views < 1 || c->width < 1 || c->height < 1 || !(c->fov_x_deg > 0) ||
+        !(c->fov_x_deg < 180))
+        return LFR_ERR_INVALID_ARG;
+    const double pi = 3.14159265358979323846;
+    const double f = (0.5 * c->width) / tan(c->fov_x_deg * pi / 180.0 * 0.5);
+    for (int j = 0; j < c->num_views; ++j) {
+        double th = 0.0;
+        if (c->num_views > 1)
+            th = (-0.5 * c->span_deg + c->span_deg * (double)j / (double)(c->num_views - 1)) * pi / 180.0;
+        const double st = sin(th), ct = cos(th);
+        const double pos[3] = {c->orbit_center[0] + c->radius * st + c->rig_offset[0],
+                               c->orbit_center[1] + c->rig_offset[1],
+                               c->orbit_center[2] - c->radius * ct + c->rig_offset[2]};
+        const double R[9] = {ct, 0.0, st, 0.0, 1.0, 0.0, -st, 0.0, ct};
+        lfr_camera &o = out[j];
+        for (int k = 0; k < 9; ++k) o.R[k] = (float)R[k];
+        for (int a = 0; a < 3; ++a) o.t[a] = (float)(-(R[3 * a] * pos[0] + R[3 * a + 1] * pos[1] + R[3 * a + 2] * pos[2]));
+        o.fx = o.fy = (float)f;
+        o.cx = (float)(0.5 * c->width);
+        o.cy = (float)(0.5 * c->height);
+    }
+    return LFR_OK;
+}
+
+lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
+                      const lfr_camera *host_cams, int32_t num_cams, const lfr_render_opts *opts, float *out_device)
+{
+    CHK(begin(ctx));
+    CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
+    lfr_display *d = const_cast<lfr_display *>(display);
+    const bool timing = (opts->flags & LFR_TIMING) != 0;
+    const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
+    const bool remap = (opts->flags & LFR_REMAP) != 0;
+    const int S = opts->cluster_size;
+    ctx->stats = lfr_stats{};
+    const ViewTables vt = build_tables(d, S, cull);
+    TaskSet *ts = nullptr;
+    if (remap) CHK(get_tasks(ctx, d, S, cull, vt, &ts));
+    record(ctx, 0, timing);
+    DevTables dt;
+    CHK(upload_tables(ctx, d, host_cams, vt, &dt));
+    Binned bn;
+    CHK(project_and_bin(ctx, d, scene, dt, vt, timing, &bn));
+
+    BlendParams bp;
+    bp.W = d->W;
+    bp.H = d->H;
+    bp.tw = d->tw;
+    bp.th = d->th;
+    bp.TX = d->TX;
+    bp.M = scene->num_gaussians;
+    bp.cluster_bits = bn.cluster_bits;
+    bp.V = d->d_V;
+    bp.psi = d->d_psi;
+    bp.view_slot = dt.view_slot;
+    bp.view_cluster = dt.view_cluster;
+    bp.ranges = bn.ranges;
+    bp.vals = bn.vals;
+    bp.rec = bn.rec;
+    bp.mean2d = bn.mean2d;
+    for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
+    bp.out = out_device;
+    bp.work = nullptr;
+    const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
+    if (count) {
+        CHK(ws_get_t(ctx, kWork, 2, &bp.work));
+        HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, ctx->stream));
+    }
+    if (remap)
+        HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, ctx->stream));
+    else
+        HIPCHK(ctx, launch_blend_rowmajor(bp, ctx->stream));
+    record(ctx, 7, timing);
+    ctx->stats.pairs = bn.P;
+    ctx->stats.clusters = vt.n_clusters;
+    ctx->stats.views = vt.n_views;
+    ctx->stats.tasks = remap ? ts->n : d->T;
+    ctx->stats.workspace_bytes = ws_total(ctx);
+    if (count) {
+        unsigned long long w[2] = {0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(w, bp.work, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->stats.evals = w[0];
+        ctx->stats.blended = w[1];
+    }
+    return finish_timing(ctx, timing, 7);
+}
+
+lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
+                                          const lfr_camera *host_cams, int32_t num_cams,
+                                          const lfr_render_opts *opts, int32_t view_batch, float *out_device)
+{
+    CHK(begin(ctx));
+    CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
+    if (view_batch < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "view_batch must be >= 1");
+    lfr_display *d = const_cast<lfr_display *>(display);
+    const bool timing = (opts->flags & LFR_TIMING) != 0;
+    const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
+    ctx->stats = lfr_stats{};
+    std::vector<int> views;
+    for (int j = 0; j < d->N; ++j)
+        if (!cull || d->ref[j]) views.push_back(j);
+    const int64_t nsub = 3ll * d->W * d->H;
+    record(ctx, 0, timing);
+    float ms[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t pairs = 0;
+    for (size_t b0 = 0; b0 < views.size(); b0 += (size_t)view_batch) {
+        const int B = (int)std::min<size_t>((size_t)view_batch, views.size() - b0);
+        // every view of the batch is its own "cluster" (S = 1) and view slot
+        ViewTables vt;
+        vt.n_clusters = vt.n_views = B;
+        vt.view_slot.assign(d->N, -1);
+        vt.view_cluster.assign(d->N, -1);
+        vt.cv_off.push_back(0);
+        for (int b = 0; b < B; ++b) {
+            const int j = views[b0 + b];
+            vt.cluster_rep.push_back(j);
+            vt.view_ids.push_back(j);
+            vt.cv_list.push_back(b);
+            vt.cv_off.push_back(b + 1);
+            vt.view_slot[j] = b;
+            vt.view_cluster[j] = b;
+        }
+        DevTables dt;
+        CHK(upload_tables(ctx, d, host_cams, vt, &dt));
+        Binned bn;
+        CHK(project_and_bin(ctx, d, scene, dt, vt, timing, &bn));
+        pairs += bn.P;
+        float *images;
+        CHK(ws_get_t(ctx, kImages, (size_t)B * nsub, &images));
+        FullFrameParams fp;
+        fp.W = d->W;
+        fp.H = d->H;
+        fp.tw = d->tw;
+        fp.th = d->th;
+        fp.TX = d->TX;
+        fp.TY = d->TY;
+        fp.M = scene->num_gaussians;
+        fp.n_views = B;
+        fp.cluster_bits = bn.cluster_bits;
+        fp.ranges = bn.ranges;
+        fp.vals = bn.vals;
+        fp.rec = bn.rec;
+        fp.mean2d = bn.mean2d;
+        for (int k = 0; k < 3; ++k) fp.bg[k] = opts->background[k];
+        fp.images = images;
+        HIPCHK(ctx, launch_blend_fullframe(fp, ctx->stream));
+        HIPCHK(ctx, launch_interlace(d->d_V, nsub, dt.view_slot, images, nsub, out_device, ctx->stream));
+        record(ctx, 7, timing);
+        if (timing) {
+            HIPCHK(ctx, hipEventSynchronize(ctx->ev[7]));
+            ms[0] += elapsed(ctx, 1, 2);
+            ms[1] += elapsed(ctx, 2, 3);
+            ms[2] += elapsed(ctx, 3, 4);
+            ms[3] += elapsed(ctx, 4, 5);
+            ms[4] += elapsed(ctx, 5, 6);
+            ms[5] += elapsed(ctx, 6, 7);
+        }
+    }
+    ctx->stats.pairs = pairs;
+    ctx->stats.views = (int)views.size();
+    ctx->stats.clusters = (int)views.size();
+    ctx->stats.workspace_bytes = ws_total(ctx);
+    if (timing) {
+        ctx->stats.ms_project = ms[0];
+        ctx->stats.ms_depth_sort = ms[1];
+        ctx->stats.ms_keygen = ms[2];
+        ctx->stats.ms_sort = ms[3];
+        ctx->stats.ms_ranges = ms[4];
+        ctx->stats.ms_blend = ms[5];
+        ctx->stats.ms_total = elapsed(ctx, 0, 7);
+    }
+    return LFR_OK;
+}
+
+lfr_status lfr_project(lfr_context *ctx, const lfr_scene *scene, const lfr_camera *cam, int32_t W, int32_t H,
+                       lfr_proj_record *out)
+{
+    CHK(begin(ctx));
+    CHK(check_scene(ctx, scene));
+    if (!cam || !out) return fail(ctx, LFR_ERR_INVALID_ARG, "NULL argument");
+    if (!cam_ok(*cam)) return fail(ctx, LFR_ERR_INVALID_ARG, "camera is not finite or has f <= 0");
+    if (W < 1 || H < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "bad image size");
+    void *h = nullptr, *dv = nullptr;
+    CHK(pinned_get(ctx, sizeof(DevCamera), &h));
+    CHK(ws_get(ctx, kCams, sizeof(DevCamera), &dv));
+    *(DevCamera *)h = dev_camera(*cam, W, H);
+    HIPCHK(ctx, hipMemcpyAsync(dv, h, sizeof(DevCamera), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, launch_project_records(scene_dev(scene), (const DevCamera *)dv, W, H, out, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // the pinned camera may be reused by the next call
+    return LFR_OK;
+}
+
+}  // extern "C"
+
+template <typename K>
+static lfr_status sort_pairs(lfr_context *ctx, K *keys, uint32_t *vals, int64_t n, int32_t b0, int32_t b1)
+{
+    CHK(begin(ctx));
+    const int kb = (int)(8 * sizeof(K));
+    if (n < 0 || (n > 0 && (!keys || !vals)) || b0 < 0 || b1 > kb || b0 > b1)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "bad sort arguments");
+    if (n > (int64_t)0xFFFFFFFFll) return fail(ctx, LFR_ERR_UNSUPPORTED, "n exceeds 2^32");
+    if (n <= 1 || b0 == b1) return LFR_OK;
+    K *k1;
+    uint32_t *v1;
+    void *tmp;
+    CHK(ws_get_t(ctx, kPairK1, (size_t)n * sizeof(K) / sizeof(uint32_t) + 2, (uint32_t **)&k1));
+    CHK(ws_get_t(ctx, kPairV1, (size_t)n, &v1));
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(n), &tmp));
+    bool alt = false;
+    hipError_t e;
+    if (sizeof(K) == 4)
+        e = radix_sort_u32((uint32_t *)keys, vals, (uint32_t *)k1, v1, n, b0, b1, tmp, &alt, ctx->stream);
+    else
+        e = radix_sort_u64((uint64_t *)keys, vals, (uint64_t *)k1, v1, n, b0, b1, tmp, &alt, ctx->stream);
+    HIPCHK(ctx, e);
+    if (alt) {
+        HIPCHK(ctx, hipMemcpyAsync(keys, k1, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(vals, v1, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return LFR_OK;
+}
+
+extern "C" {
+
+lfr_status lfr_sort_pairs_u32(lfr_context *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t b0, int32_t b1)
+{
+    return sort_pairs<uint32_t>(ctx, keys, vals, n, b0, b1);
+}
+
+lfr_status lfr_sort_pairs_u64(lfr_context *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t b0, int32_t b1)
+{
+    return sort_pairs<uint64_t>(ctx, keys, vals, n, b0, b1);
+}
+
+}  // extern "C"

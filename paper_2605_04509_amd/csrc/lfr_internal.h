@@ -1,0 +1,182 @@
+// Internal declarations shared by the liblfr HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lfr.h"
+
+namespace lfr {
+
+// ---------------------------------------------------------------------------
+// Method constants (paper section 4.3 Eq. 10 and the 3DGS conventions the
+// paper inherits from gsplat).
+// ---------------------------------------------------------------------------
+constexpr float kAlphaMin = 1.0f / 255.0f;  // alpha cutoff
+constexpr float kAlphaMax = 0.99f;          // alpha clamp
+constexpr float kTStop = 1e-4f;             // transmittance stop
+constexpr float kNearZ = 0.2f;              // near plane on the float32 depth
+constexpr double kDilation = 0.3;           // 2D covariance dilation
+constexpr double kClampFov = 1.3;           // Jacobian clamp (x tan(fov/2))
+constexpr double kHalfLog2e = 0.5 * 1.44269504088896340736;
+constexpr int kMaxClusterViews = 32;        // views unioned per cluster
+constexpr int kMaxWaveViews = 8;            // distinct views in one blend wavefront
+constexpr int kWave = 64;
+
+// Camera in double precision, with the derived clamp limits and centre.
+struct DevCamera {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double limx, limy;
+    double campos[3];
+};
+
+// Per-(cluster, Gaussian) blend record: a = (A', beta, G', opacity),
+// c = (r, g, b, unused).
+struct GaussRec {
+    float4 a;
+    float4 c;
+};
+
+// A blend work item: up to 64 subpixels of one tile that all belong to one
+// cluster and to at most kMaxWaveViews distinct views, contiguous in Psi.
+struct Task {
+    uint32_t tile;
+    uint32_t cluster;  // compact cluster index
+    uint32_t start;    // first position in Psi
+    uint32_t count;    // 1..64
+};
+
+// Per-render cluster/view tables (device copies live in the context).
+struct ViewTables {
+    int n_clusters = 0;          // K'
+    int n_views = 0;             // N' (views whose means are projected)
+    std::vector<int32_t> cluster_rep;     // [K'] original view id of the representative
+    std::vector<int32_t> cv_off;          // [K'+1] offsets into cv_list
+    std::vector<int32_t> cv_list;         // compact view slots unioned per cluster
+    std::vector<int32_t> view_ids;        // [N'] original view id per slot
+    std::vector<int32_t> view_slot;       // [N] slot of view j (-1 if none)
+    std::vector<int32_t> view_cluster;    // [N] compact cluster of view j (-1 if none)
+    std::vector<int32_t> cam_index;       // [K'+N'] camera per projected slot
+};
+
+struct TaskSet {
+    Task *d_tasks = nullptr;
+    int n = 0;
+    int32_t *d_view_cluster = nullptr;    // [N]
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All enqueue on `s`.
+// ---------------------------------------------------------------------------
+struct ViewMapParams {
+    int32_t W, H, N;
+    int64_t qa;   // Q           (multiplies 3x+u)
+    int64_t qb;   // Q*3*tan     (multiplies y)
+    int64_t qc;   // Q*K_offset
+    int64_t P;    // Q*L_x
+};
+hipError_t launch_view_map(const ViewMapParams &p, uint16_t *V, hipStream_t s);
+hipError_t launch_referenced_views(const uint16_t *V, int64_t n, uint32_t *mask, hipStream_t s);
+hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_t *psi,
+                        hipStream_t s);
+hipError_t launch_task_count(const uint16_t *V, const uint32_t *psi, const int32_t *view_cluster,
+                             int W, int H, int tw, int th, uint32_t *counts, hipStream_t s);
+hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_t *view_cluster,
+                            int W, int H, int tw, int th, const uint32_t *offsets, Task *tasks,
+                            hipStream_t s);
+
+struct SceneDev {
+    int64_t M;
+    int32_t deg;
+    const float *means, *log_scales, *quats, *opac, *sh;
+};
+struct ProjectOut {
+    GaussRec *rec;      // [K'][M]
+    float2 *ext;        // [K'][M]  conservative half extents (pixels)
+    uint64_t *dkey;     // [K'][M]  (cluster << 32) | depth bits, 0xFFFFFFFF if invalid
+    uint32_t *dval;     // [K'][M]  Gaussian index
+    float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
+};
+hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, int W, int H,
+                          int n_clusters, const int32_t *cluster_cam, int n_views,
+                          const int32_t *view_cam, const ProjectOut &out, hipStream_t s);
+hipError_t launch_project_records(const SceneDev &sc, const DevCamera *cam, int W, int H,
+                                  lfr_proj_record *out, hipStream_t s);
+
+// Exclusive scan of uint32 -> uint32 with the 64-bit total written to *total.
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, void *temp,
+                                 uint64_t *total, hipStream_t s);
+
+// Stable LSD radix sort on bits [b0, b1) with 8-bit digits; ping-pong
+// between (k0, v0) and (k1, v1).  Returns in *result_in_alt whether the
+// sorted data ended in (k1, v1).
+size_t sort_temp_bytes(int64_t n);
+hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
+hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
+                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
+
+struct BinParams {
+    int64_t M;
+    int n_clusters;
+    int W, H, tw, th, TX, TY;
+    int cluster_bits;
+    const int32_t *cv_off;    // [K'+1]
+    const int32_t *cv_list;   // compact view slots
+};
+hipError_t launch_tile_count(const BinParams &bp, const float2 *mean2d, const float2 *ext,
+                             const uint64_t *dkey, uint32_t *counts, hipStream_t s);
+hipError_t launch_gather_counts(const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                                int64_t M, int64_t n, const uint32_t *counts,
+                                uint32_t *counts_sorted, hipStream_t s);
+hipError_t launch_tile_emit(const BinParams &bp, const float2 *mean2d, const float2 *ext,
+                            const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                            const uint32_t *offsets, const uint32_t *counts_sorted, uint32_t *pair_keys,
+                            uint32_t *pair_vals, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s);
+
+struct BlendParams {
+    int W, H, tw, th, TX;
+    int64_t M;
+    int cluster_bits;
+    const uint16_t *V;
+    const uint32_t *psi;
+    const int32_t *view_slot;     // [N] compact mean slot of view j
+    const int32_t *view_cluster;  // [N] compact cluster of view j
+    const uint2 *ranges;
+    const uint32_t *vals;         // sorted Gaussian indices
+    const GaussRec *rec;          // [K'][M]
+    const float2 *mean2d;         // [N'][M]
+    float bg[3];
+    float *out;                   // [H][W][3]
+    unsigned long long *work;     // [2] evals, blended (counting variant only)
+};
+hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
+                              hipStream_t s);
+hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
+
+struct FullFrameParams {
+    int W, H, tw, th, TX, TY;
+    int64_t M;
+    int n_views;                  // views in this batch
+    int cluster_bits;
+    const uint2 *ranges;
+    const uint32_t *vals;
+    const GaussRec *rec;          // [B][M]
+    const float2 *mean2d;         // [B][M]
+    float bg[3];
+    float *images;                // [B][H][W][3]
+};
+hipError_t launch_blend_fullframe(const FullFrameParams &fp, hipStream_t s);
+hipError_t launch_interlace(const uint16_t *V, int64_t n_sub, const int32_t *view_batch_slot,
+                            const float *images, int64_t image_stride, float *out, hipStream_t s);
+
+}  // namespace lfr

@@ -1,0 +1,351 @@
+// Projection with cross-view attribute reuse (section 4.2 Eq. 5-6, appendix
+// B.2 "Projection"): per Gaussian, the 2D mean for every projected view and
+// the 2D covariance, depth and SH colour once per cluster, at the cluster's
+// representative view.
+//
+// Layout: one thread per Gaussian.  It loads the Gaussian's parameters once
+// (SH coefficients stay in registers), builds the 3D covariance once, and
+// then loops over the projected views (means) and clusters (full records),
+// writing each output plane [slot][M] coalesced across the wavefront.
+//
+// Arithmetic is IEEE double with FMA contraction disabled (the library is
+// built with -ffp-contract=off); results are rounded to float32 once, when
+// stored.  The evaluation order of every expression is fixed (it is spelled
+// out in the comments) so that two correct implementations of these
+// formulas round to the same float32 values.
+#include "lfr_internal.h"
+
+namespace lfr {
+
+struct Cov3 {
+    double xx, xy, xz, yy, yz, zz;
+};
+
+// Sigma = M M^T with M = R(q) diag(exp(log_scale)), q normalized.
+__device__ inline Cov3 cov3d(const float ls[3], const float q[4])
+{
+    double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    const double qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+    qw = qw / qn;
+    qx = qx / qn;
+    qy = qy / qn;
+    qz = qz / qn;
+    const double r00 = 1.0 - 2.0 * (qy * qy + qz * qz), r01 = 2.0 * (qx * qy - qw * qz),
+                 r02 = 2.0 * (qx * qz + qw * qy);
+    const double r10 = 2.0 * (qx * qy + qw * qz), r11 = 1.0 - 2.0 * (qx * qx + qz * qz),
+                 r12 = 2.0 * (qy * qz - qw * qx);
+    const double r20 = 2.0 * (qx * qz - qw * qy), r21 = 2.0 * (qy * qz + qw * qx),
+                 r22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+    const double s0 = exp((double)ls[0]), s1 = exp((double)ls[1]), s2 = exp((double)ls[2]);
+    const double m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
+    const double m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
+    const double m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
+    Cov3 c;
+    c.xx = (m00 * m00 + m01 * m01) + m02 * m02;
+    c.xy = (m00 * m10 + m01 * m11) + m02 * m12;
+    c.xz = (m00 * m20 + m01 * m21) + m02 * m22;
+    c.yy = (m10 * m10 + m11 * m11) + m12 * m12;
+    c.yz = (m10 * m20 + m11 * m21) + m12 * m22;
+    c.zz = (m20 * m20 + m21 * m21) + m22 * m22;
+    return c;
+}
+
+// Real SH basis (Condon-Shortley phase, m = -l..l) at unit direction (x,y,z),
+// dotted with the coefficients of one channel: acc = sum_b Y_b * sh_b.
+template <int DEG>
+__device__ inline void sh_colour(const float *shc, double x, double y, double z, float col[3])
+{
+    constexpr double pi = 3.14159265358979323846;
+    double Y[16];
+    Y[0] = 0.5 * __builtin_sqrt(1.0 / pi);
+    if (DEG >= 1) {
+        const double c1 = __builtin_sqrt(3.0 / (4.0 * pi));
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
+    }
+    if (DEG >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        const double c2a = 0.5 * __builtin_sqrt(15.0 / pi);
+        const double c2b = 0.25 * __builtin_sqrt(5.0 / pi);
+        const double c2c = 0.25 * __builtin_sqrt(15.0 / pi);
+        Y[4] = c2a * (x * y);
+        Y[5] = -c2a * (y * z);
+        Y[6] = c2b * (2.0 * zz - xx - yy);
+        Y[7] = -c2a * (x * z);
+        Y[8] = c2c * (xx - yy);
+        if (DEG >= 3) {
+            const double c3a = 0.25 * __builtin_sqrt(35.0 / (2.0 * pi));
+            const double c3b = 0.5 * __builtin_sqrt(105.0 / pi);
+            const double c3c = 0.25 * __builtin_sqrt(21.0 / (2.0 * pi));
+            const double c3d = 0.25 * __builtin_sqrt(7.0 / pi);
+            const double c3e = 0.25 * __builtin_sqrt(105.0 / pi);
+            Y[9] = -c3a * (y * (3.0 * xx - yy));
+            Y[10] = c3b * (x * y * z);
+            Y[11] = -c3c * (y * (4.0 * zz - xx - yy));
+            Y[12] = c3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+            Y[13] = -c3c * (x * (4.0 * zz - xx - yy));
+            Y[14] = c3e * (z * (xx - yy));
+            Y[15] = -c3a * (x * (xx - 3.0 * yy));
+        }
+    }
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc = acc + Y[b] * (double)shc[b * 3 + u];
+        acc = acc + 0.5;
+        col[u] = (float)(acc > 0.0 ? acc : 0.0);
+    }
+}
+
+struct MeanProj {
+    double tx, ty, tz, ux, uy;
+    float depth;
+    float2 m2d;
+    bool valid;  // finite and in front of the near plane
+};
+
+// Eq. 5: camera-space point, depth and pixel position of the mean.
+__device__ inline MeanProj project_mean(const DevCamera &c, double mx, double my, double mz, bool finite)
+{
+    MeanProj p;
+    p.tx = ((c.R[0] * mx + c.R[1] * my) + c.R[2] * mz) + c.t[0];
+    p.ty = ((c.R[3] * mx + c.R[4] * my) + c.R[5] * mz) + c.t[1];
+    p.tz = ((c.R[6] * mx + c.R[7] * my) + c.R[8] * mz) + c.t[2];
+    p.depth = (float)p.tz;
+    p.valid = finite && p.depth > kNearZ;
+    p.ux = p.tx / p.tz;
+    p.uy = p.ty / p.tz;
+    p.m2d = make_float2((float)(c.fx * p.ux + c.cx), (float)(c.fy * p.uy + c.cy));
+    p.valid = p.valid && isfinite(p.m2d.x) && isfinite(p.m2d.y);
+    return p;
+}
+
+struct FullProj {
+    float conic[3];
+    float colour[3];
+    float2 ext;
+    bool valid;
+};
+
+// Eq. 4/6 at one camera: EWA 2D covariance (Jacobian at the clamped mean
+// direction, +0.3 dilation), its inverse in LDL^T form pre-scaled by
+// log2(e)/2, SH colour along camera->mean, and conservative half extents of
+// the region where alpha can reach 1/255.
+template <int DEG>
+__device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, const Cov3 &S,
+                                        double mx, double my, double mz, float o, const float *shc)
+{
+    FullProj f;
+    f.valid = false;
+    const double *R = c.R;
+    // T1 = R Sigma (rows 0..2), Vc = T1 R^T (entries used below)
+    const double s00 = S.xx, s01 = S.xy, s02 = S.xz, s11 = S.yy, s12 = S.yz, s22 = S.zz;
+    const double a00 = (R[0] * s00 + R[1] * s01) + R[2] * s02;
+    const double a01 = (R[0] * s01 + R[1] * s11) + R[2] * s12;
+    const double a02 = (R[0] * s02 + R[1] * s12) + R[2] * s22;
+    const double a10 = (R[3] * s00 + R[4] * s01) + R[5] * s02;
+    const double a11 = (R[3] * s01 + R[4] * s11) + R[5] * s12;
+    const double a12 = (R[3] * s02 + R[4] * s12) + R[5] * s22;
+    const double a20 = (R[6] * s00 + R[7] * s01) + R[8] * s02;
+    const double a21 = (R[6] * s01 + R[7] * s11) + R[8] * s12;
+    const double a22 = (R[6] * s02 + R[7] * s12) + R[8] * s22;
+    const double v00 = (a00 * R[0] + a01 * R[1]) + a02 * R[2];
+    const double v01 = (a00 * R[3] + a01 * R[4]) + a02 * R[5];
+    const double v02 = (a00 * R[6] + a01 * R[7]) + a02 * R[8];
+    const double v11 = (a10 * R[3] + a11 * R[4]) + a12 * R[5];
+    const double v12 = (a10 * R[6] + a11 * R[7]) + a12 * R[8];
+    const double v20 = (a20 * R[0] + a21 * R[1]) + a22 * R[2];
+    const double v21 = (a20 * R[3] + a21 * R[4]) + a22 * R[5];
+    const double v22 = (a20 * R[6] + a21 * R[7]) + a22 * R[8];
+    const double cxl = m.ux < -c.limx ? -c.limx : (m.ux > c.limx ? c.limx : m.ux);
+    const double cyl = m.uy < -c.limy ? -c.limy : (m.uy > c.limy ? c.limy : m.uy);
+    const double j00 = c.fx / m.tz, j02 = -(c.fx * cxl) / m.tz;
+    const double j11 = c.fy / m.tz, j12 = -(c.fy * cyl) / m.tz;
+    const double k00 = j00 * v00 + j02 * v20;
+    const double k01 = j00 * v01 + j02 * v21;
+    const double k02 = j00 * v02 + j02 * v22;
+    const double k11 = j11 * v11 + j12 * v21;
+    const double k12 = j11 * v12 + j12 * v22;
+    const double sa = (k00 * j00 + k02 * j02) + kDilation;
+    const double sb = k01 * j11 + k02 * j12;
+    const double sc = (k11 * j11 + k12 * j12) + kDilation;
+    const double det = sa * sc - sb * sb;
+    if (!(det > 0.0)) return f;
+    const double A = sc / det, beta = -sb / sc, G = 1.0 / sc;
+    f.conic[0] = (float)(A * kHalfLog2e);
+    f.conic[1] = (float)beta;
+    f.conic[2] = (float)(G * kHalfLog2e);
+    // colour
+    double dx = mx - c.campos[0], dy = my - c.campos[1], dz = mz - c.campos[2];
+    const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
+    dx = dx / dn;
+    dy = dy / dn;
+    dz = dz / dn;
+    sh_colour<DEG>(shc, dx, dy, dz, f.colour);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite(f.conic[k]) && isfinite(f.colour[k]);
+    ok = ok && f.conic[0] > 0.0f && f.conic[2] > 0.0f;
+    if (!ok) return f;
+    // Extents of {d : o 2^-E(d) >= 1/255}, i.e. d^T Sigma^-1 d <= tau with
+    // tau = 2 ln(255 o), for the float32 conic actually stored, with margins
+    // that dominate the float32 evaluation error of the blend.
+    double tau = 2.0 * log(255.0 * (double)o);
+    tau = (tau > 0.0 ? tau : 0.0) + 0.01;
+    const double Ar = (double)f.conic[0] / kHalfLog2e, br = (double)f.conic[1],
+                 Gr = (double)f.conic[2] / kHalfLog2e;
+    const double S00 = 1.0 / Ar + br * br / Gr, S11 = 1.0 / Gr;
+    f.ext = make_float2((float)(sqrt(tau * S00) * 1.0001 + 0.02), (float)(sqrt(tau * S11) * 1.0001 + 0.02));
+    f.valid = isfinite(f.ext.x) && isfinite(f.ext.y);
+    return f;
+}
+
+struct GaussIn {
+    float mu[3], ls[3], q[4], o;
+    bool finite;
+};
+
+template <int DEG>
+__device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, float *shc)
+{
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        g.mu[k] = sc.means[3 * i + k];
+        g.ls[k] = sc.log_scales[3 * i + k];
+        fin = fin && isfinite(g.mu[k]) && isfinite(g.ls[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        g.q[k] = sc.quats[4 * i + k];
+        fin = fin && isfinite(g.q[k]);
+    }
+    g.o = sc.opac[i];
+    fin = fin && isfinite(g.o);
+    const float *s = sc.sh + (int64_t)NB * 3 * i;
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) {
+        shc[k] = s[k];
+        fin = fin && isfinite(shc[k]);
+    }
+    g.finite = fin;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams,
+                                                      int n_clusters, const int32_t *__restrict__ cluster_cam,
+                                                      int n_views, const int32_t *__restrict__ view_cam,
+                                                      ProjectOut out)
+{
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.M) return;
+    const int64_t M = sc.M;
+    GaussIn g;
+    float shc[NB * 3];
+    load_gaussian<DEG>(sc, i, g, shc);
+    const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
+    const float nanf_ = __builtin_nanf("");
+
+    for (int v = 0; v < n_views; ++v) {
+        const DevCamera &c = cams[view_cam[v]];
+        const MeanProj m = project_mean(c, mx, my, mz, g.finite);
+        out.mean2d[(int64_t)v * M + i] = m.valid ? m.m2d : make_float2(nanf_, nanf_);
+    }
+    const bool want_cov = g.finite && g.o >= kAlphaMin;
+    Cov3 S = {};
+    if (want_cov) S = cov3d(g.ls, g.q);
+    for (int k = 0; k < n_clusters; ++k) {
+        const DevCamera &c = cams[cluster_cam[k]];
+        const MeanProj m = project_mean(c, mx, my, mz, g.finite);
+        FullProj f;
+        f.valid = false;
+        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
+        const int64_t idx = (int64_t)k * M + i;
+        out.dval[idx] = (uint32_t)i;
+        if (f.valid) {
+            GaussRec r;
+            r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
+            r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
+            out.rec[idx] = r;
+            out.ext[idx] = f.ext;
+            out.dkey[idx] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(m.depth);
+        } else {
+            out.dkey[idx] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
+        }
+    }
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) project_records_kernel(SceneDev sc, const DevCamera *__restrict__ cam,
+                                                              lfr_proj_record *out)
+{
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.M) return;
+    GaussIn g;
+    float shc[NB * 3];
+    load_gaussian<DEG>(sc, i, g, shc);
+    const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
+    const MeanProj m = project_mean(*cam, mx, my, mz, g.finite);
+    lfr_proj_record r;
+    const float nanf_ = __builtin_nanf("");
+    r.mean2d[0] = m.valid ? m.m2d.x : nanf_;
+    r.mean2d[1] = m.valid ? m.m2d.y : nanf_;
+    r.depth = m.depth;
+    r.opacity = g.o;
+    r.valid_mean = m.valid ? 1 : 0;
+    r.valid = 0;
+    for (int k = 0; k < 3; ++k) r.conic[k] = r.color[k] = 0.0f;
+    if (m.valid && g.o >= kAlphaMin) {
+        const Cov3 S = cov3d(g.ls, g.q);
+        const FullProj f = project_full<DEG>(*cam, m, S, mx, my, mz, g.o, shc);
+        if (f.valid) {
+            for (int k = 0; k < 3; ++k) {
+                r.conic[k] = f.conic[k];
+                r.color[k] = f.colour[k];
+            }
+            r.valid = 1;
+        }
+    }
+    out[i] = r;
+}
+
+hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, int W, int H, int n_clusters,
+                          const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
+                          const ProjectOut &out, hipStream_t s)
+{
+    (void)W;
+    (void)H;
+    if (sc.M == 0) return hipSuccess;
+    const dim3 grid((unsigned)((sc.M + 255) / 256)), block(256);
+    switch (sc.deg) {
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_records(const SceneDev &sc, const DevCamera *cam, int W, int H,
+                                  lfr_proj_record *out, hipStream_t s)
+{
+    (void)W;
+    (void)H;
+    if (sc.M == 0) return hipSuccess;
+    const dim3 grid((unsigned)((sc.M + 255) / 256)), block(256);
+    switch (sc.deg) {
+    case 0: hipLaunchKernelGGL(project_records_kernel<0>, grid, block, 0, s, sc, cam, out); break;
+    case 1: hipLaunchKernelGGL(project_records_kernel<1>, grid, block, 0, s, sc, cam, out); break;
+    case 2: hipLaunchKernelGGL(project_records_kernel<2>, grid, block, 0, s, sc, cam, out); break;
+    default: hipLaunchKernelGGL(project_records_kernel<3>, grid, block, 0, s, sc, cam, out); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lfr

@@ -1,0 +1,380 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer and index work (view map, remap LUT, sort) must be bit-exact;
+projected attributes are computed in double precision on both sides and
+must round to the same float32 values; rendered subpixels follow the rule
+in tests/_parity.py.  Every test prints what it runs before it runs it."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._parity import colour_bound, compare
+from workloads import DisplayParams, Rational, Scene, get_workload
+from workloads.cameras import orbit_rig, pack_cameras
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_04509_amd import lfr
+    ctx = lfr.Context(0)
+    yield lfr, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _display(lfr, ctx, params):
+    return lfr.Display(ctx, params)
+
+
+# --------------------------------------------------------------------------
+# display precompute: bit-exact
+# --------------------------------------------------------------------------
+
+DISPLAYS = [
+    get_workload("tiny").display,
+    get_workload("display").display,
+    get_workload("outdoor").display,
+    DisplayParams(250, 139, 7, Rational(-3, 11), Rational(17, 3), Rational(-5, 7), 8, 8),
+    DisplayParams(250, 139, 11, Rational(1, 6), Rational(23, 5), Rational(1, 2), 32, 32),
+    DisplayParams(77, 41, 9, Rational(2, 7), Rational(9, 2), Rational(0), 16, 8),
+    DisplayParams(1, 1, 3, Rational(1, 6), Rational(5), Rational(0), 8, 8),
+]
+
+
+@pytest.mark.parametrize("k", range(len(DISPLAYS)))
+def test_view_map_and_remap_bit_exact(lib, k):
+    lfr, ctx = lib
+    p = DISPLAYS[k]
+    say("display", p)
+    d = _display(lfr, ctx, p)
+    V = d.view_map()
+    Vo = oracle.view_map(p)
+    np.testing.assert_array_equal(V, Vo)
+    psi = d.remap()
+    np.testing.assert_array_equal(psi, oracle.remap(p, Vo))
+    n, mask = d.referenced_views()
+    assert n == len(np.unique(Vo)) and mask[np.unique(Vo)].all()
+    d.close()
+
+
+def test_display_from_map_and_errors(lib):
+    lfr, ctx = lib
+    p = DisplayParams(33, 17, 5, Rational(1, 6), Rational(23, 5), tile_w=8, tile_h=8)
+    Vo = oracle.view_map(p)
+    d = lfr.Display(ctx, view_map=Vo, width=33, height=17, num_views=5, tile=(8, 8))
+    np.testing.assert_array_equal(d.view_map(), Vo)
+    np.testing.assert_array_equal(d.remap(), oracle.remap(p, Vo))
+    d.close()
+    bad = Vo.copy()
+    bad[0, 0, 0] = 5
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.Display(ctx, view_map=bad, width=33, height=17, num_views=5, tile=(8, 8))
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.Display(ctx, DisplayParams(33, 17, 5, Rational(1, 6), Rational(23, 5), tile_w=12, tile_h=8))
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+
+
+# --------------------------------------------------------------------------
+# device sort: bit-exact against a stable argsort
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,bits,wide", [(1, 32, False), (1000, 32, False), (123457, 19, False),
+                                         (300001, 13, False), (200003, 40, True), (65536, 64, True),
+                                         (4097, 7, False)])
+def test_radix_sort_stable(lib, n, bits, wide):
+    lfr, ctx = lib
+    say("sort", n, bits, wide)
+    rng = np.random.default_rng(n + bits)
+    hi = 1 << min(bits, 63)
+    keys = rng.integers(0, hi, n, dtype=np.uint64)
+    keys[: n // 3] = keys[n // 2]                    # plenty of ties
+    if not wide:
+        keys = keys.astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    kd = torch.from_numpy(keys.view(np.int64 if wide else np.int32).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    lfr.sort_pairs(ctx, kd, vd, 0, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kd.cpu().numpy().view(keys.dtype), keys[order])
+    np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+# --------------------------------------------------------------------------
+# projection: float32 roundings of the double-precision projection agree
+# --------------------------------------------------------------------------
+
+def _check_projection(gpu, ref, label):
+    np.testing.assert_array_equal(gpu["valid"], ref["valid"], err_msg=label)
+    np.testing.assert_array_equal(gpu["valid_mean"], ref["valid_mean"], err_msg=label)
+    np.testing.assert_array_equal(gpu["depth"], ref["depth"], err_msg=label)
+    vm = ref["valid_mean"] == 1
+    v = ref["valid"] == 1
+    mism = 0
+    for f, mask in (("mean2d", vm), ("conic", v), ("color", v)):
+        a, b = gpu[f][mask], ref[f][mask]
+        mism += int((a != b).sum())
+        ulp = np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64))
+        assert ulp.max(initial=0) <= 1, f"{label}: {f} differs by {ulp.max()} ulp"
+    total = int(vm.sum() * 2 + v.sum() * 6)
+    assert mism <= max(2, 1e-5 * total), f"{label}: {mism} of {total} float32 values differ by an ulp"
+    return mism
+
+
+@pytest.mark.parametrize("name,views", [("tiny", (0, 7, 15)), ("display", (0, 22)), ("outdoor", (50,))])
+def test_projection_matches_oracle(lib, name, views):
+    lfr, ctx = lib
+    w = get_workload(name)
+    say("projection", name, views)
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    ds = lfr.DeviceScene.from_numpy(scene)
+    for j in views:
+        gpu = lfr.project(ctx, ds, cams[j], w.display.width, w.display.height)
+        ref = oracle.project(scene, cams[j], w.display.width, w.display.height)
+        _check_projection(gpu, ref, f"{name} view {j}")
+
+
+def test_projection_edge_cases(lib):
+    lfr, ctx = lib
+    say("projection edge cases")
+    m = [[0, 0, 4], [0, 0, -4], [0, 0, 0.1], [0, 0, 4], [np.nan, 0, 4], [50, 0, 1], [0, 0, 4]]
+    o = [0.5, 0.5, 0.5, 1 / 255 * 0.999, 0.5, 0.5, 0.9]
+    ls = [[-3] * 3] * 6 + [[-30, -30, -30]]
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    sc = Scene(f32(m), f32(ls), f32([[1, 0, 0, 0]] * 7), f32(o), f32(np.zeros((7, 16, 3))), 3)
+    cam = pack_cameras(orbit_rig(1, 64, 36, 4.0, 0.0))[0]
+    gpu = lfr.project(ctx, lfr.DeviceScene.from_numpy(sc), cam, 64, 36)
+    ref = oracle.project(sc, cam, 64, 36)
+    _check_projection(gpu, ref, "edge")
+
+
+# --------------------------------------------------------------------------
+# rendering
+# --------------------------------------------------------------------------
+
+def _render(lfr, ctx, disp, dscene, cams, **kw):
+    out = lfr.render(ctx, disp, dscene, cams, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def tiny_setup(lib):
+    lfr, ctx = lib
+    w = get_workload("tiny")
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    V = oracle.view_map(w.display)
+    return w, scene, cams, V, lfr.DeviceScene.from_numpy(scene)
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_tiny_full_frame_parity(lib, tiny_setup, S):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("tiny full frame S =", S)
+    d = _display(lfr, ctx, w.display)
+    img = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=True)
+    ref, flags, tflag = oracle.render_frame(scene, cams, w.display, V, S)
+    info = compare(img, ref, flags, tflag, colour_bound(scene), label=f"tiny S={S}")
+    say(info)
+    # remap changes only the thread order, never a value
+    img2 = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=False)
+    np.testing.assert_array_equal(img, img2)
+    # culling unreferenced views changes nothing either
+    img3 = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=True, cull=False)
+    np.testing.assert_array_equal(img, img3)
+    d.close()
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8)])
+def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("tiling", tile)
+    d16 = _display(lfr, ctx, w.display)
+    dt = _display(lfr, ctx, w.display.with_tile(*tile))
+    for S in (1, 4):
+        a = _render(lfr, ctx, d16, ds, cams, cluster_size=S)
+        b = _render(lfr, ctx, dt, ds, cams, cluster_size=S)
+        np.testing.assert_array_equal(a, b)
+    d16.close()
+    dt.close()
+
+
+def test_fullframe_interlace_equals_exact_path(lib, tiny_setup):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("full-frame + interlace vs exact path")
+    d = _display(lfr, ctx, w.display)
+    exact = _render(lfr, ctx, d, ds, cams, cluster_size=1)
+    for vb in (1, 5, 16):
+        ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=vb)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ff.cpu().numpy(), exact)
+    ff_all = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=7, cull=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ff_all.cpu().numpy(), exact)
+    d.close()
+
+
+def test_ragged_panel_and_background(lib):
+    lfr, ctx = lib
+    say("ragged panel 250x139, tiles 32x32 / 8x8, background")
+    w = get_workload("tiny")
+    scene = w.make_scene().subset(np.arange(0, 2000, 2))
+    bg = (0.25, 0.5, 1.0)
+    for tile in ((32, 32), (8, 8)):
+        p = DisplayParams(250, 139, 11, Rational(1, 6), Rational(23, 5), Rational(1, 2), *tile)
+        cams = pack_cameras(orbit_rig(11, 250, 139, 4.0, 30.0))
+        V = oracle.view_map(p)
+        d = _display(lfr, ctx, p)
+        ds = lfr.DeviceScene.from_numpy(scene)
+        for S in (1, 3):
+            img = _render(lfr, ctx, d, ds, cams, cluster_size=S, background=bg)
+            rng = np.random.default_rng(S)
+            samples = rng.choice(V.size, 4000, replace=False)
+            ref, flags, tflag = oracle.render_subpixels(scene, cams, p, V, S, samples, bg)
+            compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene) + 1.0,
+                    label=f"ragged {tile} S={S}")
+        d.close()
+
+
+def test_degenerate_scenes(lib):
+    lfr, ctx = lib
+    say("degenerate scenes")
+    p = DisplayParams(40, 24, 5, Rational(1, 6), Rational(23, 5))
+    cams = pack_cameras(orbit_rig(5, 40, 24, 4.0, 20.0))
+    d = _display(lfr, ctx, p)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    bg = (0.1, 0.2, 0.3)
+    # empty scene -> background everywhere
+    empty = Scene(f32(np.zeros((0, 3))), f32(np.zeros((0, 3))), f32(np.zeros((0, 4))), f32(np.zeros(0)),
+                  f32(np.zeros((0, 1, 3))), 0)
+    img = _render(lfr, ctx, d, lfr.DeviceScene.from_numpy(empty), cams, cluster_size=2, background=bg)
+    np.testing.assert_array_equal(img, np.broadcast_to(np.float32(bg), img.shape))
+    # everything behind the cameras or transparent -> background
+    behind = Scene(f32([[0, 0, -5], [0, 0, 4]]), f32([[-2] * 3] * 2), f32([[1, 0, 0, 0]] * 2),
+                   f32([0.9, 0.001]), f32(np.ones((2, 1, 3))), 0)
+    img = _render(lfr, ctx, d, lfr.DeviceScene.from_numpy(behind), cams, cluster_size=1, background=bg)
+    np.testing.assert_array_equal(img, np.broadcast_to(np.float32(bg), img.shape))
+    # one large opaque Gaussian, cluster size larger than the view count
+    one = Scene(f32([[0, 0, 4]]), f32([[-0.5] * 3]), f32([[1, 0, 0, 0]]), f32([0.97]), f32([[[0.7, 0.1, 0.3]]]), 0)
+    V = oracle.view_map(p)
+    for S in (1, 8):
+        img = _render(lfr, ctx, d, lfr.DeviceScene.from_numpy(one), cams, cluster_size=S, background=bg)
+        ref, flags, tflag = oracle.render_frame(one, cams, p, V, S, bg)
+        compare(img, ref, flags, tflag, 2.0, label=f"one S={S}")
+    d.close()
+
+
+def test_capacity_limit_and_recovery(lib, tiny_setup):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("capacity limit")
+    c2 = lfr.Context(0)
+    d = _display(lfr, c2, w.display)
+    c2.set_limit(1 << 16)
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.render(c2, d, ds, cams, cluster_size=2)
+    assert ei.value.code == lfr.LFR_ERR_CAPACITY
+    c2.set_limit(0)
+    img = lfr.render(c2, d, ds, cams, cluster_size=2)
+    torch.cuda.synchronize()
+    ref = _render(lfr, ctx, d, ds, cams, cluster_size=2)
+    np.testing.assert_array_equal(img.cpu().numpy(), ref)
+    d.close()
+    c2.close()
+
+
+def test_invalid_arguments_rejected(lib, tiny_setup):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("invalid arguments")
+    d = _display(lfr, ctx, w.display)
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.render(ctx, d, ds, cams[:5], cluster_size=2)      # wrong camera count
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    bad = cams.copy()
+    bad[3, 12] = 0.0                                          # fx = 0
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.render(ctx, d, ds, bad, cluster_size=2)
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.render(ctx, d, ds, cams, cluster_size=0)
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.render(ctx, d, ds, cams, cluster_size=33)
+    assert ei.value.code == lfr.LFR_ERR_UNSUPPORTED
+    d.close()
+
+
+def _sample_in_views(V, views, per_view, seed):
+    rng = np.random.default_rng(seed)
+    flat = V.reshape(-1)
+    out = []
+    for j in views:
+        idx = np.flatnonzero(flat == j)
+        out.append(rng.choice(idx, min(per_view, idx.size), replace=False))
+    return np.sort(np.concatenate(out))
+
+
+@pytest.mark.parametrize("S", [1, 8])
+def test_display_workload_sampled(lib, S):
+    lfr, ctx = lib
+    w = get_workload("display")
+    say("display workload (200k Gaussians, 1920x1080, 45 views) S =", S)
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    V = oracle.view_map(w.display)
+    d = _display(lfr, ctx, w.display)
+    ds = lfr.DeviceScene.from_numpy(scene)
+    img = _render(lfr, ctx, d, ds, cams, cluster_size=S)
+    views = [0, 22] if S == 1 else [18, 22]          # S = 8: both in cluster 2 (rep 20)
+    samples = _sample_in_views(V, views, 600, S)
+    ref, flags, tflag = oracle.render_subpixels(scene, cams, w.display, V, S, samples)
+    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), label=f"display S={S}")
+    say(info)
+    if S == 1:
+        ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=10)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ff.cpu().numpy(), img)
+    d.close()
+
+
+def test_outdoor_workload_bench_configuration(lib):
+    """3M Gaussians, 100 views, 3840x2160, cluster size 8, remap on: the
+    configuration the benchmark times, checked on sampled subpixels."""
+    lfr, ctx = lib
+    w = get_workload("outdoor")
+    say("outdoor workload (3M Gaussians, 4K, 100 views) S = 8")
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    V = oracle.view_map(w.display)
+    d = _display(lfr, ctx, w.display)
+    ds = lfr.DeviceScene.from_numpy(scene)
+    img = _render(lfr, ctx, d, ds, cams, cluster_size=8)
+    st = ctx.stats()
+    say(st)
+    samples = _sample_in_views(V, [48, 51], 100, 3)   # cluster 6 (views 48..55, rep 52)
+    ref, flags, tflag = oracle.render_subpixels(scene, cams, w.display, V, 8, samples)
+    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
+                   label="outdoor S=8")
+    say(info)
+    assert np.isfinite(img).all()
+    d.close()
