@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 METRIC = "interlaced LF frames/s (4K, 100 views) reuse+remap vs plain; fwd+bwd ms"
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6: 256 CUs x 64 lanes x FMA x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
 FLOPS_PER_EVAL = 14      # alpha: dx,dy (2) + w fma (2) + A'w, G'dy, *dy (3) + fma (2) + exp2 (1)
                          #        + o*e (1) + min (1) + cutoff test (1)
 FLOPS_PER_BLEND = 6      # 1-a, T*(1-a), stop test, c*a, fma (2)
@@ -135,7 +136,9 @@ def main():
         frame(timing=True)
     sync()
     # timed region: K frames; per-stage HIP events on the library's stream
-    stages = {k: 0.0 for k in ("ms_project", "ms_depth_sort", "ms_keygen", "ms_sort", "ms_ranges", "ms_blend")}
+    stages = {k: 0.0 for k in ("ms_project", "ms_depth_sort", "ms_keygen", "ms_sort", "ms_ranges", "ms_blend",
+                               "ms_sort_scatter")}
+    scatter_launches = 0
     sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -143,18 +146,28 @@ def main():
         st = ctx.stats()
         for k in stages:
             stages[k] += st[k]
+        scatter_launches += st["sort_scatter_launches"]
     sync()
     sec = (time.perf_counter() - t0) / args.steps
     stages = {k: v / args.steps for k, v in stages.items()}
     fps = 1.0 / sec
     log(f"reuse+remap S={S}: {sec * 1e3:.3f} ms/frame, {fps:.1f} frames/s, stages {stages}")
 
+    # the dominant kernel: the blend (one launch per frame) or the scatter of
+    # the tile sort (one launch per radix pass)
     flops = FLOPS_PER_EVAL * work["evals"] + FLOPS_PER_BLEND * work["blended"]
-    achieved = flops / (stages["ms_blend"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "blend_remap_kernel", "achieved": achieved,
-                "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS, "traffic": None,
-                "evals": work["evals"], "blended": work["blended"], "launch_ms": stages["ms_blend"]}
+    blend_alu = {"bound": "alu", "kernel": "blend_remap_kernel", "launch_ms": stages["ms_blend"],
+                 "achieved": flops / (stages["ms_blend"] * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
+                 "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"], "traffic": None}
+    blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
+    per_launch = stages["ms_sort_scatter"] * args.steps / max(scatter_launches, 1)
+    scatter = {"bound": "hbm", "kernel": "sort_scatter_kernel<uint32_t> (tile sort)", "launch_ms": per_launch,
+               "achieved": 16.0 * work["pairs"] / (per_launch * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "bytes_per_launch": 16 * work["pairs"], "traffic": None}
+    scatter["frac"] = scatter["achieved"] / scatter["peak"]
+    dominant_is_sort = stages["ms_sort_scatter"] > stages["ms_blend"]
+    roofline = scatter if dominant_is_sort else blend_alu
+    other = blend_alu if dominant_is_sort else scatter
 
     result = {
         "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
@@ -167,7 +180,7 @@ def main():
                                 f"tile {w.display.tile_w}x{w.display.tile_h}"),
                    "cluster_size": S, "remap": True, "parallelism": "single GPU"},
         "stages_ms": stages, "pairs": work["pairs"], "clusters": work["clusters"], "views": work["views"],
-        "roofline": roofline, "fwd_bwd_ms": None,
+        "roofline": roofline, "roofline_other": other, "fwd_bwd_ms": None,
     }
 
     if not args.no_ablation:
@@ -184,10 +197,14 @@ def main():
         plain = {}
         for label, cull in (("all_views", False), ("referenced_views", True)):
             best = None
-            for vb in (10, 25, 50):
+            for vb in (5, 10, 20):
                 def pf(vb=vb, cull=cull):
                     lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out)
-                pf()
+                try:
+                    pf()
+                except lfr.LfrError as e:         # e.g. more pairs than 32-bit offsets hold
+                    log(f"plain {label} batch {vb}: {e}")
+                    continue
                 t = timed(pf, 1, sync)
                 log(f"plain {label} batch {vb}: {t * 1e3:.1f} ms")
                 if best is None or t < best[1]:

@@ -114,6 +114,8 @@ typedef struct {
     float ms_project, ms_depth_sort, ms_keygen, ms_sort, ms_ranges, ms_blend, ms_total;
     uint64_t evals;            /* (subpixel, Gaussian) alphas evaluated (LFR_COUNT_WORK) */
     uint64_t blended;          /* of those, contributions blended               */
+    float ms_sort_scatter;     /* LFR_TIMING: scatter launches of the tile sort */
+    int32_t sort_scatter_launches;
 } lfr_stats;
 
 /* One projected Gaussian (48 bytes), as returned by lfr_project:

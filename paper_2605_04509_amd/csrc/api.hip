@@ -38,7 +38,8 @@ struct lfr_context {
     void *pinned = nullptr;
     size_t pinned_n = 0;
     hipEvent_t ev[8] = {};
-    bool events = false;
+    hipEvent_t sort_ev[2 * kSortTimedPasses] = {};
+    int sort_timed = 0;
 };
 
 struct lfr_display {
@@ -378,7 +379,8 @@ lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_sce
     HIPCHK(ctx, launch_tile_emit(bp, po.mean2d, po.ext, dks, dvs, offsets, counts_sorted, pk0, pv0, s));
     record(ctx, 4, timing);
     bool palt = false;
-    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, cbits, cbits + tbits, sort_temp, &palt, s));
+    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, cbits, cbits + tbits, sort_temp, &palt, s,
+                               timing ? ctx->sort_ev : nullptr, &ctx->sort_timed));
     const uint32_t *keys = palt ? pk1 : pk0;
     record(ctx, 5, timing);
     const int64_t n_ranges = (int64_t)d->T << cbits;
@@ -473,6 +475,14 @@ lfr_status finish_timing(lfr_context *ctx, bool timing, int last)
     ctx->stats.ms_ranges = elapsed(ctx, 5, 6);
     ctx->stats.ms_blend = elapsed(ctx, 6, 7);
     ctx->stats.ms_total = elapsed(ctx, 0, 7);
+    float scat = 0.f;
+    for (int p = 0; p < ctx->sort_timed; ++p) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->sort_ev[2 * p], ctx->sort_ev[2 * p + 1]) == hipSuccess) scat += ms;
+        else (void)hipGetLastError();
+    }
+    ctx->stats.ms_sort_scatter = scat;
+    ctx->stats.sort_scatter_launches = ctx->sort_timed;
     return LFR_OK;
 }
 
@@ -501,6 +511,11 @@ lfr_status lfr_context_create(int32_t device, void *hip_stream, lfr_context **ou
             lfr_context_destroy(ctx);
             return LFR_ERR_HIP;
         }
+    for (auto &e : ctx->sort_ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            lfr_context_destroy(ctx);
+            return LFR_ERR_HIP;
+        }
     *out = ctx;
     return LFR_OK;
 }
@@ -514,6 +529,8 @@ void lfr_context_destroy(lfr_context *ctx)
         if (b.p) (void)hipFree(b.p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->sort_ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
 }

@@ -118,8 +118,12 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, v
 // between (k0, v0) and (k1, v1).  Returns in *result_in_alt whether the
 // sorted data ended in (k1, v1).
 size_t sort_temp_bytes(int64_t n);
+// With `ev` non-null, events ev[2p], ev[2p+1] bracket the scatter launch of
+// pass p (at most kSortTimedPasses passes are timed).
+constexpr int kSortTimedPasses = 4;
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
+                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s,
+                          hipEvent_t *ev = nullptr, int *n_timed = nullptr);
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
 

@@ -104,9 +104,11 @@ size_t sort_temp_bytes(int64_t n)
 
 template <typename K>
 static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                                  void *temp, bool *in_alt, hipStream_t s)
+                                  void *temp, bool *in_alt, hipStream_t s, hipEvent_t *ev = nullptr,
+                                  int *n_timed = nullptr)
 {
     *in_alt = false;
+    if (n_timed) *n_timed = 0;
     if (n <= 1 || b1 <= b0) return hipSuccess;
     const int64_t nb = sort_tiles(n);
     const int64_t nh = 256 * nb;
@@ -122,8 +124,15 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
                            hist, nb);
         hipError_t e = launch_exclusive_scan(hist, offs, nh, stemp, nullptr, s);
         if (e != hipSuccess) return e;
+        const int pass = (shift - b0) / 8;
+        const bool timed = ev && pass < kSortTimedPasses;
+        if (timed) (void)hipEventRecord(ev[2 * pass], s);
         hipLaunchKernelGGL(sort_scatter_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, vi, ko, vo, n,
                            shift, mask, offs, nb);
+        if (timed) {
+            (void)hipEventRecord(ev[2 * pass + 1], s);
+            *n_timed = pass + 1;
+        }
         K *tk = ki;
         ki = ko;
         ko = tk;
@@ -136,9 +145,9 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
 }
 
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s)
+                          void *temp, bool *in_alt, hipStream_t s, hipEvent_t *ev, int *n_timed)
 {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s);
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, ev, n_timed);
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,

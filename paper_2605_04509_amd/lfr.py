@@ -67,7 +67,8 @@ class lfr_stats(Structure):
                 ("clusters", c_int32), ("views", c_int32), ("tasks", c_int32), ("reserved", c_int32),
                 ("ms_project", c_float), ("ms_depth_sort", c_float), ("ms_keygen", c_float),
                 ("ms_sort", c_float), ("ms_ranges", c_float), ("ms_blend", c_float),
-                ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64)]
+                ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64),
+                ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
