@@ -160,10 +160,17 @@ def main():
                  "achieved": flops / (stages["ms_blend"] * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
                  "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"], "traffic": None}
     blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
-    per_launch = stages["ms_sort_scatter"] * args.steps / max(scatter_launches, 1)
+    # tile sort: every chunk's pairs pass through ceil(tile_bits / 8) scatter
+    # launches, each reading and writing (key, value) = 16 B per pair
+    d = w.display
+    n_tiles = -(-d.width // d.tile_w) * -(-d.height // d.tile_h)
+    passes = -(-max(1, (n_tiles - 1).bit_length()) // 8)
+    launches = max(scatter_launches / args.steps, 1.0)
+    per_launch = stages["ms_sort_scatter"] / launches
+    bytes_per_launch = 16.0 * work["pairs"] * passes / launches
     scatter = {"bound": "hbm", "kernel": "sort_scatter_kernel<uint32_t> (tile sort)", "launch_ms": per_launch,
-               "achieved": 16.0 * work["pairs"] / (per_launch * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "bytes_per_launch": 16 * work["pairs"], "traffic": None}
+               "launches_per_frame": launches, "achieved": bytes_per_launch / (per_launch * 1e-3) / 1e9,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_launch": bytes_per_launch, "traffic": None}
     scatter["frac"] = scatter["achieved"] / scatter["peak"]
     dominant_is_sort = stages["ms_sort_scatter"] > stages["ms_blend"]
     roofline = scatter if dominant_is_sort else blend_alu
@@ -179,7 +186,8 @@ def main():
                                 f"{w.display.tan_slant.den}, pitch {w.display.pitch.num}/{w.display.pitch.den}, "
                                 f"tile {w.display.tile_w}x{w.display.tile_h}"),
                    "cluster_size": S, "remap": True, "parallelism": "single GPU"},
-        "stages_ms": stages, "pairs": work["pairs"], "clusters": work["clusters"], "views": work["views"],
+        "stages_ms": stages, "pairs": work["pairs"], "chunks": work["chunks"], "clusters": work["clusters"],
+        "views": work["views"],
         "roofline": roofline, "roofline_other": other, "fwd_bwd_ms": None,
     }
 

@@ -100,17 +100,20 @@ typedef struct {
     int32_t cluster_size;   /* S >= 1; 1 = exact path, no reuse           */
     uint32_t flags;         /* LFR_* bits above                            */
     float background[3];    /* added as T_final * background per channel   */
+    int32_t first_chunk;    /* depth ranks per cluster in the first chunk;
+                               later chunks grow 4x; 0 = max(4096, M/256).
+                               Changes only the amount of work, never the
+                               image.                                       */
 } lfr_render_opts;
 
 /* Counters and timings of the last render on a context. */
 typedef struct {
-    uint64_t pairs;            /* Gaussian-(tile, cluster) pairs sorted        */
-    uint64_t projected;        /* Gaussian-cluster projections kept (valid)    */
+    uint64_t pairs;            /* Gaussian-(tile, cluster) pairs sorted, all chunks */
     uint64_t workspace_bytes;  /* device workspace currently held              */
     int32_t clusters;          /* clusters rendered (K')                       */
     int32_t views;             /* views whose means were projected (N')        */
     int32_t tasks;             /* blend work items (wavefronts or tiles)       */
-    int32_t reserved;
+    int32_t chunks;            /* depth chunks binned and blended              */
     float ms_project, ms_depth_sort, ms_keygen, ms_sort, ms_ranges, ms_blend, ms_total;
     uint64_t evals;            /* (subpixel, Gaussian) alphas evaluated (LFR_COUNT_WORK) */
     uint64_t blended;          /* of those, contributions blended               */

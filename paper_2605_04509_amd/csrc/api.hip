@@ -13,12 +13,17 @@
 
 using namespace lfr;
 
+// First depth chunk: max(kFirstChunk, M / kFirstChunkDiv) ranks per cluster;
+// each following chunk is 4x longer.
+constexpr int64_t kFirstChunk = 4096;
+constexpr int64_t kFirstChunkDiv = 256;
+
 namespace {
 
 enum Slot {
     kRec, kExt, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
-    kWork, kNumSlots
+    kWork, kAlive, kAliveBits, kState, kTaskAlive, kNumSlots
 };
 
 struct Buf {
@@ -37,9 +42,7 @@ struct lfr_context {
     Buf ws[kNumSlots];
     void *pinned = nullptr;
     size_t pinned_n = 0;
-    hipEvent_t ev[8] = {};
-    hipEvent_t sort_ev[2 * kSortTimedPasses] = {};
-    int sort_timed = 0;
+    Timer timer;
 };
 
 struct lfr_display {
@@ -270,46 +273,22 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
     return LFR_OK;
 }
 
-void record(lfr_context *ctx, int k, bool timing)
-{
-    if (timing) (void)hipEventRecord(ctx->ev[k], ctx->stream);
-}
-
-float elapsed(lfr_context *ctx, int a, int b)
-{
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0.f;
-    }
-    return ms;
-}
-
-lfr_status read_total(lfr_context *ctx, const uint64_t *d_total, uint64_t *host)
-{
-    void *h = nullptr;
-    CHK(pinned_get(ctx, 64, &h));
-    HIPCHK(ctx, hipMemcpyAsync(h, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    *host = *(uint64_t *)h;
-    return LFR_OK;
-}
-
-// Project -> count -> depth sort -> scan -> emit -> tile sort -> ranges.
-// On success the sorted pair values and the ranges are in the outputs.
-struct Binned {
-    uint64_t P = 0;
-    uint32_t *vals = nullptr;
-    uint2 *ranges = nullptr;
+// Project every Gaussian for the clusters and views of `vt`, then sort each
+// cluster's Gaussians by depth (key = cluster << 32 | float32 depth bits).
+struct Projected {
     GaussRec *rec = nullptr;
+    float2 *ext = nullptr;
     float2 *mean2d = nullptr;
-    int cluster_bits = 0;
+    const uint64_t *dks = nullptr;
+    const uint32_t *dvs = nullptr;
+    int cbits = 0, tbits = 0;
 };
 
-lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_scene *scene, const DevTables &dt,
-                           const ViewTables &vt, bool timing, Binned *out)
+lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_scene *scene, const DevTables &dt,
+                            const ViewTables &vt, Projected *out)
 {
     hipStream_t s = ctx->stream;
+    Timer &tm = ctx->timer;
     const int64_t M = scene->num_gaussians;
     const int KC = vt.n_clusters, NV = vt.n_views;
     const int64_t MK = M * KC;
@@ -319,12 +298,10 @@ lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_sce
         return fail(ctx, LFR_ERR_UNSUPPORTED, "tile (%d bits) + cluster (%d bits) keys exceed 32 bits", tbits, cbits);
     if (MK > (int64_t)0xFFFFFFFFll)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "Gaussians x clusters = %lld exceeds 2^32", (long long)MK);
-
     ProjectOut po;
-    uint32_t *counts, *counts_sorted, *offsets;
-    uint64_t *dkey1, *d_total;
+    uint64_t *dkey1;
     uint32_t *dval1;
-    void *scan_temp, *sort_temp;
+    void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
     CHK(ws_get_t(ctx, kExt, MK, &po.ext));
     CHK(ws_get_t(ctx, kDKey0, MK, &po.dkey));
@@ -332,19 +309,30 @@ lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_sce
     CHK(ws_get_t(ctx, kDKey1, MK, &dkey1));
     CHK(ws_get_t(ctx, kDVal1, MK, &dval1));
     CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
-    CHK(ws_get_t(ctx, kCounts, MK, &counts));
-    CHK(ws_get_t(ctx, kCountsSorted, MK, &counts_sorted));
-    CHK(ws_get_t(ctx, kOffsets, MK, &offsets));
-    CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(MK), &scan_temp));
-    CHK(ws_get_t(ctx, kTotal, 8, &d_total));
-
-    record(ctx, 1, timing);
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MK), &sort_temp));
+    const size_t e0 = tm.mark(s);
     HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, d->W, d->H, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
-    record(ctx, 2, timing);
+    const size_t e1 = tm.mark(s);
+    tm.span(kStProject, e0, e1);
+    bool alt = false;
+    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MK, 0, 32 + cbits, sort_temp, &alt, s));
+    tm.span(kStDepthSort, e1, tm.mark(s));
+    out->rec = po.rec;
+    out->ext = po.ext;
+    out->mean2d = po.mean2d;
+    out->dks = alt ? dkey1 : po.dkey;
+    out->dvs = alt ? dval1 : po.dval;
+    out->cbits = cbits;
+    out->tbits = tbits;
+    return LFR_OK;
+}
 
+BinParams bin_params(const lfr_display *d, const DevTables &dt, const ViewTables &vt, int64_t M, int cbits,
+                     const uint32_t *alive)
+{
     BinParams bp;
     bp.M = M;
-    bp.n_clusters = KC;
+    bp.n_clusters = vt.n_clusters;
     bp.W = d->W;
     bp.H = d->H;
     bp.tw = d->tw;
@@ -354,52 +342,84 @@ lfr_status project_and_bin(lfr_context *ctx, const lfr_display *d, const lfr_sce
     bp.cluster_bits = cbits;
     bp.cv_off = dt.cv_off;
     bp.cv_list = dt.cv_list;
-    HIPCHK(ctx, launch_tile_count(bp, po.mean2d, po.ext, po.dkey, counts, s));
+    bp.alive = alive;
+    bp.alive_words = (d->TX + 31) / 32;
+    return bp;
+}
 
-    // per-cluster depth order: sort (cluster << 32 | depth bits, i)
-    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MK), &sort_temp));
-    bool alt = false;
-    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MK, 0, 32 + cbits, sort_temp, &alt, s));
-    const uint64_t *dks = alt ? dkey1 : po.dkey;
-    const uint32_t *dvs = alt ? dval1 : po.dval;
-    record(ctx, 3, timing);
-    HIPCHK(ctx, launch_gather_counts(dks, dvs, M, MK, counts, counts_sorted, s));
-    HIPCHK(ctx, launch_exclusive_scan(counts_sorted, offsets, MK, scan_temp, d_total, s));
+// Device-side totals: [0] pair count of the last scan (u64), [1] low word:
+// unsaturated subpixels of the frame (u32).
+struct Totals {
+    uint64_t pairs;
+    uint32_t alive;
+    uint32_t pad;
+};
+
+// One depth chunk: pair count -> scan -> (host readback) -> emit -> stable
+// sort on the tile bits -> list ranges.
+struct Chunk {
     uint64_t P = 0;
-    CHK(read_total(ctx, d_total, &P));
-    if (P >= 0xFFFFFFFFull)
-        return fail(ctx, LFR_ERR_UNSUPPORTED, "%llu Gaussian-tile pairs exceed 2^32", (unsigned long long)P);
+    uint32_t alive = 0;
+    const uint32_t *vals = nullptr;
+    uint2 *ranges = nullptr;
+};
 
+lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr, int64_t r0, int64_t len,
+                     Totals *d_tot, Chunk *out)
+{
+    hipStream_t s = ctx->stream;
+    Timer &tm = ctx->timer;
+    const int64_t n = len * bp.n_clusters;
+    uint32_t *counts, *offsets;
+    void *scan_temp;
+    CHK(ws_get_t(ctx, kCounts, n, &counts));
+    CHK(ws_get_t(ctx, kOffsets, n, &offsets));
+    CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(n), &scan_temp));
+    const size_t e0 = tm.mark(s);
+    HIPCHK(ctx, launch_chunk_count(bp, pr.mean2d, pr.ext, pr.dks, pr.dvs, r0, len, counts, s));
+    HIPCHK(ctx, launch_exclusive_scan(counts, offsets, n, scan_temp, &d_tot->pairs, s));
+    void *h = nullptr;
+    CHK(pinned_get(ctx, sizeof(Totals), &h));
+    HIPCHK(ctx, hipMemcpyAsync(h, d_tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const Totals ht = *(const Totals *)h;
+    if (ht.pairs >= 0xFFFFFFFFull)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "%llu Gaussian-tile pairs in one chunk exceed 2^32",
+                    (unsigned long long)ht.pairs);
+    const uint64_t P = ht.pairs;
     uint32_t *pk0, *pv0, *pk1, *pv1;
+    void *sort_temp;
     CHK(ws_get_t(ctx, kPairK0, P, &pk0));
     CHK(ws_get_t(ctx, kPairV0, P, &pv0));
     CHK(ws_get_t(ctx, kPairK1, P, &pk1));
     CHK(ws_get_t(ctx, kPairV1, P, &pv1));
-    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)MK)), &sort_temp));
-    HIPCHK(ctx, launch_tile_emit(bp, po.mean2d, po.ext, dks, dvs, offsets, counts_sorted, pk0, pv0, s));
-    record(ctx, 4, timing);
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.M * bp.n_clusters))),
+               &sort_temp));
+    HIPCHK(ctx, launch_chunk_emit(bp, pr.mean2d, pr.ext, pr.dks, pr.dvs, r0, len, counts, offsets, pk0, pv0, s));
+    const size_t e1 = tm.mark(s);
+    tm.span(kStKeygen, e0, e1);
     bool palt = false;
-    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, cbits, cbits + tbits, sort_temp, &palt, s,
-                               timing ? ctx->sort_ev : nullptr, &ctx->sort_timed));
+    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, bp.cluster_bits, bp.cluster_bits + bits_for(
+                                   (int64_t)bp.TX * bp.TY), sort_temp, &palt, s, &tm));
     const uint32_t *keys = palt ? pk1 : pk0;
-    record(ctx, 5, timing);
-    const int64_t n_ranges = (int64_t)d->T << cbits;
+    const size_t e2 = tm.mark(s);
+    tm.span(kStSort, e1, e2);
+    const int64_t n_ranges = ((int64_t)bp.TX * bp.TY) << bp.cluster_bits;
     uint2 *ranges;
     CHK(ws_get_t(ctx, kRanges, n_ranges, &ranges));
     HIPCHK(ctx, launch_fill_u32((uint32_t *)ranges, 0u, 2 * n_ranges, s));
     HIPCHK(ctx, launch_ranges(keys, (int64_t)P, ranges, s));
-    record(ctx, 6, timing);
-
+    tm.span(kStRanges, e2, tm.mark(s));
     out->P = P;
+    out->alive = ht.alive;
     out->vals = palt ? pv1 : pv0;
     out->ranges = ranges;
-    out->rec = po.rec;
-    out->mean2d = po.mean2d;
-    out->cluster_bits = cbits;
     return LFR_OK;
 }
 
-lfr_status get_tasks(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
+// Blend work items and per-(tile, cluster) subpixel counts for cluster
+// size S, built once per display.
+lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
 {
     const int64_t key = (int64_t)S * 2 + (cull ? 1 : 0);
     auto it = d->tasks.find(key);
@@ -409,8 +429,14 @@ lfr_status get_tasks(lfr_context *ctx, lfr_display *d, int S, bool cull, const V
     }
     hipStream_t s = ctx->stream;
     TaskSet ts;
+    ts.cluster_bits = bits_for(vt.n_clusters);
+    const int64_t n_tc = (int64_t)d->T << ts.cluster_bits;
     HIPCHK(ctx, hipMalloc(&ts.d_view_cluster, sizeof(int32_t) * d->N));
     HIPCHK(ctx, hipMemcpy(ts.d_view_cluster, vt.view_cluster.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMalloc(&ts.d_tc_count, sizeof(uint32_t) * n_tc));
+    HIPCHK(ctx, launch_fill_u32(ts.d_tc_count, 0u, n_tc, s));
+    HIPCHK(ctx, launch_tc_count(d->d_V, ts.d_view_cluster, d->W, d->H, d->tw, d->th, ts.cluster_bits,
+                                ts.d_tc_count, s));
     uint32_t *cnt = nullptr, *off = nullptr;
     uint64_t *tot = nullptr;
     void *tmp = nullptr;
@@ -456,6 +482,7 @@ lfr_status check_render_args(lfr_context *ctx, const lfr_display *d, const lfr_s
         if (!cam_ok(cams[j])) return fail(ctx, LFR_ERR_INVALID_ARG, "camera %d is not finite or has f <= 0", j);
     if (!opts) return fail(ctx, LFR_ERR_INVALID_ARG, "opts is NULL");
     if (opts->cluster_size < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "cluster_size must be >= 1");
+    if (opts->first_chunk < 0) return fail(ctx, LFR_ERR_INVALID_ARG, "first_chunk must be >= 0");
     if (opts->cluster_size > kMaxClusterViews)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "cluster_size %d > %d", opts->cluster_size, kMaxClusterViews);
     for (float b : opts->background)
@@ -464,25 +491,25 @@ lfr_status check_render_args(lfr_context *ctx, const lfr_display *d, const lfr_s
     return LFR_OK;
 }
 
-lfr_status finish_timing(lfr_context *ctx, bool timing, int last)
+lfr_status finish_timing(lfr_context *ctx)
 {
-    if (!timing) return LFR_OK;
-    HIPCHK(ctx, hipEventSynchronize(ctx->ev[last]));
-    ctx->stats.ms_project = elapsed(ctx, 1, 2);
-    ctx->stats.ms_depth_sort = elapsed(ctx, 2, 3);
-    ctx->stats.ms_keygen = elapsed(ctx, 3, 4);
-    ctx->stats.ms_sort = elapsed(ctx, 4, 5);
-    ctx->stats.ms_ranges = elapsed(ctx, 5, 6);
-    ctx->stats.ms_blend = elapsed(ctx, 6, 7);
-    ctx->stats.ms_total = elapsed(ctx, 0, 7);
-    float scat = 0.f;
-    for (int p = 0; p < ctx->sort_timed; ++p) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ctx->sort_ev[2 * p], ctx->sort_ev[2 * p + 1]) == hipSuccess) scat += ms;
-        else (void)hipGetLastError();
-    }
-    ctx->stats.ms_sort_scatter = scat;
-    ctx->stats.sort_scatter_launches = ctx->sort_timed;
+    const Timer &tm = ctx->timer;
+    if (!tm.on || tm.used == 0) return LFR_OK;
+    HIPCHK(ctx, hipEventSynchronize(tm.pool[tm.used - 1]));
+    float ms[kNumStages];
+    tm.sum(ms);
+    lfr_stats &st = ctx->stats;
+    st.ms_project = ms[kStProject];
+    st.ms_depth_sort = ms[kStDepthSort];
+    st.ms_keygen = ms[kStKeygen];
+    st.ms_sort = ms[kStSort];
+    st.ms_ranges = ms[kStRanges];
+    st.ms_blend = ms[kStBlend];
+    st.ms_sort_scatter = ms[kStScatter];
+    st.ms_total = ms[kStTotal];
+    int n = 0;
+    for (const auto &sp : tm.spans) n += sp.stage == kStScatter;
+    st.sort_scatter_launches = n;
     return LFR_OK;
 }
 
@@ -506,16 +533,6 @@ lfr_status lfr_context_create(int32_t device, void *hip_stream, lfr_context **ou
     lfr_context *ctx = new lfr_context();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
-    for (auto &e : ctx->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            lfr_context_destroy(ctx);
-            return LFR_ERR_HIP;
-        }
-    for (auto &e : ctx->sort_ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            lfr_context_destroy(ctx);
-            return LFR_ERR_HIP;
-        }
     *out = ctx;
     return LFR_OK;
 }
@@ -528,10 +545,6 @@ void lfr_context_destroy(lfr_context *ctx)
     for (Buf &b : ctx->ws)
         if (b.p) (void)hipFree(b.p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto &e : ctx->sort_ev)
-        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -701,6 +714,7 @@ void lfr_display_destroy(lfr_display *d)
     for (auto &kv : d->tasks) {
         if (kv.second.d_tasks) (void)hipFree(kv.second.d_tasks);
         if (kv.second.d_view_cluster) (void)hipFree(kv.second.d_view_cluster);
+        if (kv.second.d_tc_count) (void)hipFree(kv.second.d_tc_count);
     }
     delete d;
 }
@@ -767,19 +781,42 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     CHK(begin(ctx));
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
     lfr_display *d = const_cast<lfr_display *>(display);
-    const bool timing = (opts->flags & LFR_TIMING) != 0;
+    hipStream_t s = ctx->stream;
     const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
     const bool remap = (opts->flags & LFR_REMAP) != 0;
+    const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
     const int S = opts->cluster_size;
+    const int64_t M = scene->num_gaussians;
+    const int64_t nsub = 3ll * d->W * d->H;
     ctx->stats = lfr_stats{};
+    Timer &tm = ctx->timer;
     const ViewTables vt = build_tables(d, S, cull);
     TaskSet *ts = nullptr;
-    if (remap) CHK(get_tasks(ctx, d, S, cull, vt, &ts));
-    record(ctx, 0, timing);
+    CHK(get_layout(ctx, d, S, cull, vt, &ts));
+    tm.reset((opts->flags & LFR_TIMING) != 0);
+    const size_t t0 = tm.mark(s);
     DevTables dt;
     CHK(upload_tables(ctx, d, host_cams, vt, &dt));
-    Binned bn;
-    CHK(project_and_bin(ctx, d, scene, dt, vt, timing, &bn));
+    Projected pr;
+    CHK(project_and_sort(ctx, d, scene, dt, vt, &pr));
+
+    // traversal state: unsaturated subpixels per (tile, cluster) list and in
+    // total, the lists' alive bits, per-subpixel (T, C), per-item flags
+    const int words = (d->TX + 31) / 32;
+    const int64_t n_tc = (int64_t)d->T << pr.cbits;
+    uint32_t *tc_alive, *alive_bits;
+    float2 *state;
+    uint8_t *task_alive;
+    Totals *d_tot;
+    CHK(ws_get_t(ctx, kAlive, n_tc, &tc_alive));
+    CHK(ws_get_t(ctx, kAliveBits, (int64_t)vt.n_clusters * d->TY * words, &alive_bits));
+    CHK(ws_get_t(ctx, kState, nsub, &state));
+    CHK(ws_get_t(ctx, kTaskAlive, (size_t)std::max(ts->n, 1) + 4, &task_alive));
+    CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
+    HIPCHK(ctx, hipMemcpyAsync(tc_alive, ts->d_tc_count, sizeof(uint32_t) * n_tc, hipMemcpyDeviceToDevice, s));
+    HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
+    HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
+    HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
 
     BlendParams bp;
     bp.W = d->W;
@@ -787,42 +824,76 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     bp.tw = d->tw;
     bp.th = d->th;
     bp.TX = d->TX;
-    bp.M = scene->num_gaussians;
-    bp.cluster_bits = bn.cluster_bits;
+    bp.M = M;
+    bp.cluster_bits = pr.cbits;
     bp.V = d->d_V;
     bp.psi = d->d_psi;
     bp.view_slot = dt.view_slot;
     bp.view_cluster = dt.view_cluster;
-    bp.ranges = bn.ranges;
-    bp.vals = bn.vals;
-    bp.rec = bn.rec;
-    bp.mean2d = bn.mean2d;
+    bp.rec = pr.rec;
+    bp.mean2d = pr.mean2d;
     for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
     bp.out = out_device;
     bp.work = nullptr;
-    const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
+    bp.state = state;
+    bp.task_alive = task_alive;
+    bp.tc_alive = tc_alive;
+    bp.alive_total = &d_tot->alive;
     if (count) {
         CHK(ws_get_t(ctx, kWork, 2, &bp.work));
-        HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, ctx->stream));
+        HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, s));
     }
-    if (remap)
-        HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, ctx->stream));
-    else
-        HIPCHK(ctx, launch_blend_rowmajor(bp, ctx->stream));
-    record(ctx, 7, timing);
-    ctx->stats.pairs = bn.P;
+    const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits);
+
+    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
+    int64_t r0 = 0, len = opts->first_chunk > 0
+                              ? (int64_t)opts->first_chunk
+                              : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    bool blend_ran = false;
+    uint64_t pairs = 0;
+    int chunks = 0;
+    for (;;) {
+        len = std::min(len, M - r0);
+        const bool last = r0 + len >= M;
+        Chunk ch;
+        CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch));
+        if (blend_ran && ch.alive == 0) break;  // every subpixel saturated: all outputs written
+        ++chunks;
+        pairs += ch.P;
+        if (ch.P > 0 || last) {
+            bp.ranges = ch.ranges;
+            bp.vals = ch.vals;
+            bp.first = blend_ran ? 0 : 1;
+            bp.last = last ? 1 : 0;
+            const size_t e0 = tm.mark(s);
+            if (remap)
+                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
+            else
+                HIPCHK(ctx, launch_blend_rowmajor(bp, s));
+            if (!last)
+                HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+            tm.span(kStBlend, e0, tm.mark(s));
+            blend_ran = true;
+        }
+        if (last) break;
+        r0 += len;
+        len *= 4;
+    }
+    tm.span(kStTotal, t0, tm.mark(s));
+    ctx->stats.pairs = pairs;
+    ctx->stats.chunks = chunks;
     ctx->stats.clusters = vt.n_clusters;
     ctx->stats.views = vt.n_views;
     ctx->stats.tasks = remap ? ts->n : d->T;
     ctx->stats.workspace_bytes = ws_total(ctx);
     if (count) {
         unsigned long long w[2] = {0, 0};
-        HIPCHK(ctx, hipMemcpyAsync(w, bp.work, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(w, bp.work, sizeof w, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
         ctx->stats.evals = w[0];
         ctx->stats.blended = w[1];
     }
-    return finish_timing(ctx, timing, 7);
+    return finish_timing(ctx);
 }
 
 lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
@@ -833,15 +904,18 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
     if (view_batch < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "view_batch must be >= 1");
     lfr_display *d = const_cast<lfr_display *>(display);
-    const bool timing = (opts->flags & LFR_TIMING) != 0;
+    hipStream_t s = ctx->stream;
     const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
+    const int64_t M = scene->num_gaussians;
     ctx->stats = lfr_stats{};
+    Timer &tm = ctx->timer;
+    tm.reset((opts->flags & LFR_TIMING) != 0);
     std::vector<int> views;
     for (int j = 0; j < d->N; ++j)
         if (!cull || d->ref[j]) views.push_back(j);
     const int64_t nsub = 3ll * d->W * d->H;
-    record(ctx, 0, timing);
-    float ms[6] = {0, 0, 0, 0, 0, 0};
+    const int words = (d->TX + 31) / 32;
+    const size_t t0 = tm.mark(s);
     uint64_t pairs = 0;
     for (size_t b0 = 0; b0 < views.size(); b0 += (size_t)view_batch) {
         const int B = (int)std::min<size_t>((size_t)view_batch, views.size() - b0);
@@ -862,9 +936,18 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         }
         DevTables dt;
         CHK(upload_tables(ctx, d, host_cams, vt, &dt));
-        Binned bn;
-        CHK(project_and_bin(ctx, d, scene, dt, vt, timing, &bn));
-        pairs += bn.P;
+        Projected pr;
+        CHK(project_and_sort(ctx, d, scene, dt, vt, &pr));
+        // one chunk with every tile of every view alive
+        uint32_t *alive_bits;
+        Totals *d_tot;
+        CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * d->TY * words, &alive_bits));
+        CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
+        HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * d->TY * words, s));
+        const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits);
+        Chunk ch;
+        CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
+        pairs += ch.P;
         float *images;
         CHK(ws_get_t(ctx, kImages, (size_t)B * nsub, &images));
         FullFrameParams fp;
@@ -874,42 +957,27 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         fp.th = d->th;
         fp.TX = d->TX;
         fp.TY = d->TY;
-        fp.M = scene->num_gaussians;
+        fp.M = M;
         fp.n_views = B;
-        fp.cluster_bits = bn.cluster_bits;
-        fp.ranges = bn.ranges;
-        fp.vals = bn.vals;
-        fp.rec = bn.rec;
-        fp.mean2d = bn.mean2d;
+        fp.cluster_bits = pr.cbits;
+        fp.ranges = ch.ranges;
+        fp.vals = ch.vals;
+        fp.rec = pr.rec;
+        fp.mean2d = pr.mean2d;
         for (int k = 0; k < 3; ++k) fp.bg[k] = opts->background[k];
         fp.images = images;
-        HIPCHK(ctx, launch_blend_fullframe(fp, ctx->stream));
-        HIPCHK(ctx, launch_interlace(d->d_V, nsub, dt.view_slot, images, nsub, out_device, ctx->stream));
-        record(ctx, 7, timing);
-        if (timing) {
-            HIPCHK(ctx, hipEventSynchronize(ctx->ev[7]));
-            ms[0] += elapsed(ctx, 1, 2);
-            ms[1] += elapsed(ctx, 2, 3);
-            ms[2] += elapsed(ctx, 3, 4);
-            ms[3] += elapsed(ctx, 4, 5);
-            ms[4] += elapsed(ctx, 5, 6);
-            ms[5] += elapsed(ctx, 6, 7);
-        }
+        const size_t e0 = tm.mark(s);
+        HIPCHK(ctx, launch_blend_fullframe(fp, s));
+        HIPCHK(ctx, launch_interlace(d->d_V, nsub, dt.view_slot, images, nsub, out_device, s));
+        tm.span(kStBlend, e0, tm.mark(s));
     }
+    tm.span(kStTotal, t0, tm.mark(s));
     ctx->stats.pairs = pairs;
+    ctx->stats.chunks = 1;
     ctx->stats.views = (int)views.size();
     ctx->stats.clusters = (int)views.size();
     ctx->stats.workspace_bytes = ws_total(ctx);
-    if (timing) {
-        ctx->stats.ms_project = ms[0];
-        ctx->stats.ms_depth_sort = ms[1];
-        ctx->stats.ms_keygen = ms[2];
-        ctx->stats.ms_sort = ms[3];
-        ctx->stats.ms_ranges = ms[4];
-        ctx->stats.ms_blend = ms[5];
-        ctx->stats.ms_total = elapsed(ctx, 0, 7);
-    }
-    return LFR_OK;
+    return finish_timing(ctx);
 }
 
 lfr_status lfr_project(lfr_context *ctx, const lfr_scene *scene, const lfr_camera *cam, int32_t W, int32_t H,

@@ -1,5 +1,10 @@
 // Alpha blending (section 4.3, Eq. 9-10; appendix B.2 Alpha-Blend).
 //
+// The subpixel blends are resumable: lists arrive in depth chunks (see
+// binning.hip) and each launch continues every unsaturated subpixel from its
+// saved (T, C), in the same front-to-back order as one uninterrupted pass.
+// A subpixel's output is written when it saturates or after the last chunk.
+//
 // Every kernel here evaluates one (subpixel, Gaussian) step with the same
 // inline function, so the remapped path, the row-major path and the
 // full-frame baseline produce bit-identical values for the same inputs:
@@ -42,6 +47,15 @@ __device__ __forceinline__ void add_work(unsigned long long *dst, unsigned long 
     if ((threadIdx.x & 63) == 0) atomicAdd(dst, v);
 }
 
+// Saved per-subpixel state: (T, C), T negated once the subpixel saturated.
+__device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, float &T, float &C, bool &done)
+{
+    const float2 st = bp.state[at];
+    done = st.x < 0.0f;
+    T = fabsf(st.x);
+    C = st.y;
+}
+
 // One 64-lane wavefront per task: up to 64 subpixels of one tile and one
 // cluster, in Psi order.  Gaussians of the (tile, cluster) list are staged
 // 64 at a time into LDS (record + the mean for each distinct view of the
@@ -57,10 +71,12 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
 
     const int ti = xcd_task(blockIdx.x, per);
     if (ti >= n_tasks) return;
+    if (!bp.first && !bp.task_alive[ti]) return;
     const Task tk = tasks[ti];
     const int lane = threadIdx.x;
     const bool active = lane < (int)tk.count;
-    const uint32_t p = bp.psi[tk.start + (active ? lane : (int)tk.count - 1)];
+    const uint32_t at = tk.start + (active ? lane : (int)tk.count - 1);
+    const uint32_t p = bp.psi[at];
     const int j = bp.V[p];
     const uint32_t pix = p / 3;
     const int u = (int)(p - 3 * pix);
@@ -76,42 +92,61 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     const int n_runs = __popcll(runs);
     if (first) s_slot[my_run] = bp.view_slot[j];
 
-    const uint2 range = bp.ranges[(tk.tile << bp.cluster_bits) | tk.cluster];
+    const uint32_t list = (tk.tile << bp.cluster_bits) | tk.cluster;
+    const uint2 range = bp.ranges[list];
     const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
     float T = 1.0f, C = 0.0f;
     bool done = !active;
+    if (!bp.first && active) load_state(bp, at, T, C, done);
+    const bool was_done = done;
     unsigned long long n_eval = 0, n_blend = 0;
     __syncthreads();
-    for (uint32_t base = range.x; base < range.y; base += kWave) {
-        const int nb = (int)min((uint32_t)kWave, range.y - base);
-        if (lane < nb) {
-            const uint32_t i = bp.vals[base + lane];
-            const GaussRec g = rec[i];
-            s_a[lane] = g.a;
-            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
-            for (int q = 0; q < n_runs; ++q)
-                s_mu[q][lane] = sanitize_mean(bp.mean2d[(int64_t)s_slot[q] * bp.M + i]);
-        }
-        __syncthreads();
-        if (!done) {
-            for (int g = 0; g < nb; ++g) {
-                const float alpha = step_alpha(s_a[g], s_mu[my_run][g], px, py);
-                if (kCount) ++n_eval;
-                if (alpha < kAlphaMin) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < kTStop) {
-                    done = true;
-                    break;
-                }
-                C = fmaf(s_c[g * 4 + u] * alpha, T, C);
-                T = Tn;
-                if (kCount) ++n_blend;
+    if (__ballot(!done) != 0) {
+        for (uint32_t base = range.x; base < range.y; base += kWave) {
+            const int nb = (int)min((uint32_t)kWave, range.y - base);
+            if (lane < nb) {
+                const uint32_t i = bp.vals[base + lane];
+                const GaussRec g = rec[i];
+                s_a[lane] = g.a;
+                *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
+                for (int q = 0; q < n_runs; ++q)
+                    s_mu[q][lane] = sanitize_mean(bp.mean2d[(int64_t)s_slot[q] * bp.M + i]);
             }
+            __syncthreads();
+            if (!done) {
+                for (int g = 0; g < nb; ++g) {
+                    const float alpha = step_alpha(s_a[g], s_mu[my_run][g], px, py);
+                    if (kCount) ++n_eval;
+                    if (alpha < kAlphaMin) continue;
+                    const float Tn = T * (1.0f - alpha);
+                    if (Tn < kTStop) {
+                        done = true;
+                        break;
+                    }
+                    C = fmaf(s_c[g * 4 + u] * alpha, T, C);
+                    T = Tn;
+                    if (kCount) ++n_blend;
+                }
+            }
+            if (__ballot(!done) == 0) break;
+            __syncthreads();
         }
-        if (__ballot(!done) == 0) break;
-        __syncthreads();
     }
-    if (active) bp.out[p] = C + T * bp.bg[u];
+    const uint64_t newly = __ballot(active && done && !was_done);
+    const bool all_done = __ballot(!done) == 0;
+    if (all_done || bp.last) {
+        if (active) bp.out[p] = C + T * bp.bg[u];
+    } else if (active) {
+        bp.state[at] = make_float2(done ? -T : T, C);
+    }
+    if (lane == 0) {
+        if (all_done) bp.task_alive[ti] = 0;
+        const uint32_t nn = (uint32_t)__popcll(newly);
+        if (nn) {
+            atomicSub(&bp.tc_alive[list], nn);
+            atomicSub(bp.alive_total, nn);
+        }
+    }
     if (kCount) {
         add_work(bp.work, n_eval);
         add_work(bp.work + 1, n_blend);
@@ -120,7 +155,8 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
 
 // Row-major thread order (no remap): a 256-thread block per tile, each
 // thread takes subpixels r = tid, tid+256, ... of the tile's row-major list
-// and walks its own (tile, cluster) list from global memory.
+// and walks its own (tile, cluster) list from global memory.  State is kept
+// per panel subpixel.
 template <bool kCount>
 __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
 {
@@ -137,14 +173,20 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
         const int u = rem - 3 * lx;
         const int x = x0 + lx, y = y0 + ly;
         const uint32_t p = (uint32_t)(((int64_t)y * bp.W + x) * 3 + u);
+        float T = 1.0f, C = 0.0f;
+        bool done = false;
+        if (!bp.first) {
+            load_state(bp, p, T, C, done);
+            if (done) continue;
+        }
         const int j = bp.V[p];
         const int c = bp.view_cluster[j];
         const int slot = bp.view_slot[j];
-        const uint2 range = bp.ranges[((uint32_t)t << bp.cluster_bits) | (uint32_t)c];
+        const uint32_t list = ((uint32_t)t << bp.cluster_bits) | (uint32_t)c;
+        const uint2 range = bp.ranges[list];
         const GaussRec *rec = bp.rec + (int64_t)c * bp.M;
         const float2 *mu = bp.mean2d + (int64_t)slot * bp.M;
         const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-        float T = 1.0f, C = 0.0f;
         for (uint32_t e = range.x; e < range.y; ++e) {
             const uint32_t i = bp.vals[e];
             const GaussRec g = rec[i];
@@ -152,13 +194,23 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
             if (kCount) ++n_eval;
             if (alpha < kAlphaMin) continue;
             const float Tn = T * (1.0f - alpha);
-            if (Tn < kTStop) break;
+            if (Tn < kTStop) {
+                done = true;
+                break;
+            }
             const float col = u == 0 ? g.c.x : (u == 1 ? g.c.y : g.c.z);
             C = fmaf(col * alpha, T, C);
             T = Tn;
             if (kCount) ++n_blend;
         }
-        bp.out[p] = C + T * bp.bg[u];
+        if (done || bp.last) bp.out[p] = C + T * bp.bg[u];
+        if (done) {
+            if (!bp.last) bp.state[p] = make_float2(-T, C);
+            atomicSub(&bp.tc_alive[list], 1u);
+            atomicSub(bp.alive_total, 1u);
+        } else if (!bp.last) {
+            bp.state[p] = make_float2(T, C);
+        }
     }
     if (kCount) {
         add_work(bp.work, n_eval);

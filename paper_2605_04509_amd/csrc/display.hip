@@ -191,4 +191,28 @@ hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_
     return hipGetLastError();
 }
 
+// Subpixels of every (tile, cluster) list: one thread per subpixel.
+__global__ void __launch_bounds__(256) tc_count_kernel(const uint16_t *V, const int32_t *view_cluster, int W, int H,
+                                                        int tw, int th, int cluster_bits, uint32_t *counts)
+{
+    const int64_t n = 3ll * W * H;
+    const int TX = (W + tw - 1) / tw;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+        const int c = view_cluster[V[s]];
+        if (c < 0) continue;
+        const int64_t pix = s / 3;
+        const int y = (int)(pix / W), x = (int)(pix - (int64_t)y * W);
+        const uint32_t t = (uint32_t)((y / th) * TX + x / tw);
+        atomicAdd(&counts[(t << cluster_bits) | (uint32_t)c], 1u);
+    }
+}
+
+hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,
+                           int cluster_bits, uint32_t *counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(tc_count_kernel, dim3(grid_for(3ll * W * H, 256)), dim3(256), 0, s, V, view_cluster, W, H, tw,
+                       th, cluster_bits, counts);
+    return hipGetLastError();
+}
+
 }  // namespace lfr

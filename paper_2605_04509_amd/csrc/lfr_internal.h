@@ -65,10 +65,66 @@ struct ViewTables {
     std::vector<int32_t> cam_index;       // [K'+N'] camera per projected slot
 };
 
+// Per (display, cluster size, culling): blend work items and the number of
+// subpixels of every (tile, cluster) list.
 struct TaskSet {
     Task *d_tasks = nullptr;
     int n = 0;
     int32_t *d_view_cluster = nullptr;    // [N]
+    uint32_t *d_tc_count = nullptr;       // [T << cluster_bits]
+    int cluster_bits = 0;
+};
+
+// Stage timer: HIP events recorded on the working stream, summed per stage
+// after the frame.
+enum Stage { kStProject, kStDepthSort, kStKeygen, kStSort, kStRanges, kStBlend, kStScatter, kStTotal, kNumStages };
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Span {
+        int stage;
+        size_t a, b;
+    };
+    std::vector<Span> spans;
+    void reset(bool enable)
+    {
+        on = enable;
+        used = 0;
+        spans.clear();
+    }
+    size_t mark(hipStream_t s)
+    {
+        if (!on) return 0;
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return 0;
+            }
+            pool.push_back(e);
+        }
+        (void)hipEventRecord(pool[used], s);
+        return used++;
+    }
+    void span(int stage, size_t a, size_t b)
+    {
+        if (on) spans.push_back(Span{stage, a, b});
+    }
+    // ms per stage; out[kNumStages]; the events must have completed
+    void sum(float *out) const
+    {
+        for (int k = 0; k < kNumStages; ++k) out[k] = 0.f;
+        for (const Span &sp : spans) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[sp.a], pool[sp.b]) == hipSuccess) out[sp.stage] += ms;
+            else (void)hipGetLastError();
+        }
+    }
+    ~Timer()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -118,12 +174,10 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, v
 // between (k0, v0) and (k1, v1).  Returns in *result_in_alt whether the
 // sorted data ended in (k1, v1).
 size_t sort_temp_bytes(int64_t n);
-// With `ev` non-null, events ev[2p], ev[2p+1] bracket the scatter launch of
-// pass p (at most kSortTimedPasses passes are timed).
-constexpr int kSortTimedPasses = 4;
+// With a timer, every scatter launch is recorded as a kStScatter span.
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s,
-                          hipEvent_t *ev = nullptr, int *n_timed = nullptr);
+                          Timer *tm = nullptr);
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
 
@@ -134,18 +188,22 @@ struct BinParams {
     int cluster_bits;
     const int32_t *cv_off;    // [K'+1]
     const int32_t *cv_list;   // compact view slots
+    const uint32_t *alive;    // [K'][TY][alive_words] bit per (cluster, tile) list still needed
+    int alive_words;          // 32-bit words per tile row
 };
-hipError_t launch_tile_count(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                             const uint64_t *dkey, uint32_t *counts, hipStream_t s);
-hipError_t launch_gather_counts(const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
-                                int64_t M, int64_t n, const uint32_t *counts,
-                                uint32_t *counts_sorted, hipStream_t s);
-hipError_t launch_tile_emit(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                            const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
-                            const uint32_t *offsets, const uint32_t *counts_sorted, uint32_t *pair_keys,
-                            uint32_t *pair_vals, hipStream_t s);
+hipError_t launch_chunk_count(const BinParams &bp, const float2 *mean2d, const float2 *ext,
+                              const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0,
+                              int64_t len, uint32_t *counts, hipStream_t s);
+hipError_t launch_chunk_emit(const BinParams &bp, const float2 *mean2d, const float2 *ext,
+                             const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0,
+                             int64_t len, uint32_t *counts, const uint32_t *offsets, uint32_t *pair_keys,
+                             uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s);
+hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
+                             int cluster_bits, uint32_t *bits, hipStream_t s);
+hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,
+                           int cluster_bits, uint32_t *counts, hipStream_t s);
 
 struct BlendParams {
     int W, H, tw, th, TX;
@@ -162,6 +220,12 @@ struct BlendParams {
     float bg[3];
     float *out;                   // [H][W][3]
     unsigned long long *work;     // [2] evals, blended (counting variant only)
+    // resumable traversal over depth chunks
+    float2 *state;                // per subpixel (T, C); T < 0 once saturated
+    uint8_t *task_alive;          // per work item (remapped path)
+    uint32_t *tc_alive;           // per (tile, cluster) list: unsaturated subpixels
+    uint32_t *alive_total;        // unsaturated subpixels of the frame
+    int first, last;              // first / last chunk of the frame
 };
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
                               hipStream_t s);

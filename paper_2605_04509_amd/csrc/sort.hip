@@ -2,12 +2,8 @@
 //
 // Per pass: (1) every 4096-key tile builds a 256-bin digit histogram in LDS;
 // (2) the [digit][tile] histogram matrix is exclusive-scanned, giving every
-// (digit, tile) its first output slot; (3) every tile re-reads its keys and
-// scatters them.  Stability inside a tile comes from processing its keys in
-// index order, 256 at a time: each wavefront matches equal digits with eight
-// 64-bit ballots (one per digit bit), ranks a key by the popcount of equal
-// lanes below it, and the four wavefronts' per-digit counts are prefixed in
-// wavefront order through LDS.
+// (digit, tile) its first output slot; (3) every tile re-reads its keys,
+// ranks them stably (wavefront ballots) and writes them out in digit runs.
 #include "lfr_internal.h"
 
 namespace lfr {
@@ -34,28 +30,63 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one 4096-key tile.  Wavefront w ranks the contiguous keys
+// [tile + 1024 w, tile + 1024 (w + 1)) 64 at a time: eight ballots find the
+// lanes with an equal digit, the lane's rank is the popcount of equal lanes
+// below it plus the wavefront's running count of that digit (kept in LDS and
+// advanced by the lowest equal lane).  Wavefront counts are then prefixed in
+// wavefront order, which keeps the sort stable.  Keys are first placed into
+// an LDS copy of the tile in digit order and then written out in that order,
+// so each digit's run is written with consecutive addresses.
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                                    K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                    int64_t n, int shift, uint32_t mask,
-                                                                   const uint32_t *__restrict__ offs, int64_t nb)
+                                                                   const uint32_t *__restrict__ offs,
+                                                                   const uint32_t *__restrict__ hist, int64_t nb)
 {
-    __shared__ uint32_t base_of[256];               // next free slot per digit
-    __shared__ uint32_t wave_cnt[kSortWaves][256];  // per-wavefront counts, then offsets
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kPerWave = kSortTile / kSortWaves;  // 1024
+    constexpr int kIt = kPerWave / 64;                // 16
+    __shared__ K s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_cnt[kSortWaves][256];
+    __shared__ uint32_t s_dstart[256];  // first slot of each digit inside the tile
+    __shared__ uint32_t s_gbase[256];   // first global slot of each digit for this tile
+    __shared__ uint32_t s_wsum[kSortWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    base_of[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
     const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t idx = tile + it * kSortBlock + threadIdx.x;
-        const bool valid = idx < n;
-        K key = 0;
-        uint32_t val = 0, digit = 0;
-        if (valid) {
-            key = kin[idx];
-            val = vin[idx];
-            digit = (uint32_t)(key >> shift) & mask;
+
+    // digit starts inside the tile: exclusive scan of this tile's histogram
+    {
+        const uint32_t h = hist[(int64_t)tid * nb + blockIdx.x];
+        uint32_t incl = h;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+            if (lane >= d) incl += t;
         }
+        if (lane == 63) s_wsum[wave] = incl;
+        s_gbase[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) s_cnt[w][tid] = 0;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_wsum[w];
+        s_dstart[tid] = before + incl - h;
+    }
+    __syncthreads();
+
+    K key[kIt];
+    uint32_t val[kIt], rank[kIt];
+    const int64_t wbase = tile + (int64_t)wave * kPerWave;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t idx = wbase + it * 64 + lane;
+        const bool valid = idx < n;
+        key[it] = valid ? kin[idx] : (K)0;
+        val[it] = valid ? vin[idx] : 0u;
+        const uint32_t digit = (uint32_t)(key[it] >> shift) & mask;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -63,32 +94,41 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        const bool leader = valid && (peers & lt_mask) == 0;
-        // clear this wavefront's counters (4 per lane), then publish counts
+        const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (valid) old = s_cnt[wave][digit];
+        rank[it] = old + below;
+        if (valid && below == 0) s_cnt[wave][digit] = old + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) wave_cnt[wave][lane * 4 + k] = 0;
-        __syncthreads();
-        if (leader) wave_cnt[wave][digit] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            const int d = threadIdx.x;
-            uint32_t run = base_of[d];
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t c = s_cnt[w][tid];
+            s_cnt[w][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t c = wave_cnt[w][d];
-                wave_cnt[w][d] = run;
-                run += c;
-            }
-            base_of[d] = run;
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t idx = wbase + it * 64 + lane;
+        if (idx < n) {
+            const uint32_t digit = (uint32_t)(key[it] >> shift) & mask;
+            const uint32_t pos = s_dstart[digit] + s_cnt[wave][digit] + rank[it];
+            s_key[pos] = key[it];
+            s_val[pos] = val[it];
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = wave_cnt[wave][digit] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kSortTile, n - tile);
+    for (int p = tid; p < cnt; p += kSortBlock) {
+        const K k = s_key[p];
+        const uint32_t digit = (uint32_t)(k >> shift) & mask;
+        const uint32_t g = s_gbase[digit] + ((uint32_t)p - s_dstart[digit]);
+        kout[g] = k;
+        vout[g] = s_val[p];
     }
 }
 
@@ -104,11 +144,9 @@ size_t sort_temp_bytes(int64_t n)
 
 template <typename K>
 static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                                  void *temp, bool *in_alt, hipStream_t s, hipEvent_t *ev = nullptr,
-                                  int *n_timed = nullptr)
+                                  void *temp, bool *in_alt, hipStream_t s, Timer *tm = nullptr)
 {
     *in_alt = false;
-    if (n_timed) *n_timed = 0;
     if (n <= 1 || b1 <= b0) return hipSuccess;
     const int64_t nb = sort_tiles(n);
     const int64_t nh = 256 * nb;
@@ -124,15 +162,10 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
                            hist, nb);
         hipError_t e = launch_exclusive_scan(hist, offs, nh, stemp, nullptr, s);
         if (e != hipSuccess) return e;
-        const int pass = (shift - b0) / 8;
-        const bool timed = ev && pass < kSortTimedPasses;
-        if (timed) (void)hipEventRecord(ev[2 * pass], s);
+        const size_t ea = tm ? tm->mark(s) : 0;
         hipLaunchKernelGGL(sort_scatter_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, vi, ko, vo, n,
-                           shift, mask, offs, nb);
-        if (timed) {
-            (void)hipEventRecord(ev[2 * pass + 1], s);
-            *n_timed = pass + 1;
-        }
+                           shift, mask, offs, hist, nb);
+        if (tm) tm->span(kStScatter, ea, tm->mark(s));
         K *tk = ki;
         ki = ko;
         ko = tk;
@@ -145,9 +178,9 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
 }
 
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s, hipEvent_t *ev, int *n_timed)
+                          void *temp, bool *in_alt, hipStream_t s, Timer *tm)
 {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, ev, n_timed);
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm);
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,

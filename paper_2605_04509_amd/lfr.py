@@ -59,12 +59,13 @@ class lfr_scene(Structure):
 
 
 class lfr_render_opts(Structure):
-    _fields_ = [("cluster_size", c_int32), ("flags", c_uint32), ("background", c_float * 3)]
+    _fields_ = [("cluster_size", c_int32), ("flags", c_uint32), ("background", c_float * 3),
+                ("first_chunk", c_int32)]
 
 
 class lfr_stats(Structure):
-    _fields_ = [("pairs", c_uint64), ("projected", c_uint64), ("workspace_bytes", c_uint64),
-                ("clusters", c_int32), ("views", c_int32), ("tasks", c_int32), ("reserved", c_int32),
+    _fields_ = [("pairs", c_uint64), ("workspace_bytes", c_uint64),
+                ("clusters", c_int32), ("views", c_int32), ("tasks", c_int32), ("chunks", c_int32),
                 ("ms_project", c_float), ("ms_depth_sort", c_float), ("ms_keygen", c_float),
                 ("ms_sort", c_float), ("ms_ranges", c_float), ("ms_blend", c_float),
                 ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64),
@@ -316,14 +317,14 @@ def make_view_cone(num_views, width, height, radius, span_deg, fov_x_deg=60.0, c
 
 
 def render(ctx: Context, display: Display, scene: DeviceScene, cams, cluster_size=1, remap=True, cull=True,
-           timing=False, background=(0.0, 0.0, 0.0), out=None, count_work=False):
+           timing=False, background=(0.0, 0.0, 0.0), out=None, count_work=False, first_chunk=0):
     torch = _torch()
     if out is None:
         out = torch.empty((display.height, display.width, 3), dtype=torch.float32, device=scene.means.device)
     _require_device_f32(out, "out")
     flags = (LFR_REMAP if remap else 0) | (LFR_CULL_UNREFERENCED if cull else 0) | (LFR_TIMING if timing else 0)
     flags |= LFR_COUNT_WORK if count_work else 0
-    opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background))
+    opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background), first_chunk)
     ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
     sc = scene.c_struct()
     _check(library().lfr_render(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca), ctypes.byref(opts),
@@ -338,7 +339,7 @@ def render_fullframe_interlace(ctx: Context, display: Display, scene: DeviceScen
         out = torch.zeros((display.height, display.width, 3), dtype=torch.float32, device=scene.means.device)
     _require_device_f32(out, "out")
     flags = (LFR_CULL_UNREFERENCED if cull else 0) | (LFR_TIMING if timing else 0)
-    opts = lfr_render_opts(1, flags, (c_float * 3)(*background))
+    opts = lfr_render_opts(1, flags, (c_float * 3)(*background), 0)
     ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
     sc = scene.c_struct()
     _check(library().lfr_render_fullframe_interlace(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca),

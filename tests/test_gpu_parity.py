@@ -202,6 +202,23 @@ def test_tiny_full_frame_parity(lib, tiny_setup, S):
     d.close()
 
 
+@pytest.mark.parametrize("S,remap", [(1, True), (4, True), (4, False)])
+def test_depth_chunking_does_not_change_the_image(lib, tiny_setup, S, remap):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("depth chunks: first chunk 1 / 7 / 64 / all, S =", S, "remap", remap)
+    d = _display(lfr, ctx, w.display)
+    whole = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=remap, first_chunk=1 << 20)
+    assert ctx.stats()["chunks"] == 1
+    for fc in (1, 7, 64):
+        img = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=remap, first_chunk=fc)
+        st = ctx.stats()
+        say(fc, st["chunks"], st["pairs"])
+        assert st["chunks"] > 1
+        np.testing.assert_array_equal(img, whole)
+    d.close()
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8)])
 def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     lfr, ctx = lib
