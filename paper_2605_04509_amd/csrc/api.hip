@@ -21,7 +21,7 @@ constexpr int64_t kFirstChunkDiv = 256;
 namespace {
 
 enum Slot {
-    kRec, kExt, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
+    kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kNumSlots
 };
@@ -277,7 +277,7 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
 // cluster's Gaussians by depth (key = cluster << 32 | float32 depth bits).
 struct Projected {
     GaussRec *rec = nullptr;
-    float2 *ext = nullptr;
+    ItemRec *items = nullptr;
     float2 *mean2d = nullptr;
     const uint64_t *dks = nullptr;
     const uint32_t *dvs = nullptr;
@@ -303,7 +303,7 @@ lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_sc
     uint32_t *dval1;
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
-    CHK(ws_get_t(ctx, kExt, MK, &po.ext));
+    CHK(ws_get_t(ctx, kItems, MK, &po.items));
     CHK(ws_get_t(ctx, kDKey0, MK, &po.dkey));
     CHK(ws_get_t(ctx, kDVal0, MK, &po.dval));
     CHK(ws_get_t(ctx, kDKey1, MK, &dkey1));
@@ -311,14 +311,15 @@ lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_sc
     CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MK), &sort_temp));
     const size_t e0 = tm.mark(s);
-    HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, d->W, d->H, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
+    const TileGrid tg{d->W, d->H, d->tw, d->th, dt.cv_off, dt.cv_list};
+    HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, tg, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStProject, e0, e1);
     bool alt = false;
     HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MK, 0, 32 + cbits, sort_temp, &alt, s));
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
-    out->ext = po.ext;
+    out->items = po.items;
     out->mean2d = po.mean2d;
     out->dks = alt ? dkey1 : po.dkey;
     out->dvs = alt ? dval1 : po.dval;
@@ -328,7 +329,7 @@ lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_sc
 }
 
 BinParams bin_params(const lfr_display *d, const DevTables &dt, const ViewTables &vt, int64_t M, int cbits,
-                     const uint32_t *alive)
+                     const uint32_t *alive, const ItemRec *items)
 {
     BinParams bp;
     bp.M = M;
@@ -344,6 +345,7 @@ BinParams bin_params(const lfr_display *d, const DevTables &dt, const ViewTables
     bp.cv_list = dt.cv_list;
     bp.alive = alive;
     bp.alive_words = (d->TX + 31) / 32;
+    bp.items = items;
     return bp;
 }
 
@@ -376,7 +378,7 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     CHK(ws_get_t(ctx, kOffsets, n, &offsets));
     CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(n), &scan_temp));
     const size_t e0 = tm.mark(s);
-    HIPCHK(ctx, launch_chunk_count(bp, pr.mean2d, pr.ext, pr.dks, pr.dvs, r0, len, counts, s));
+    HIPCHK(ctx, launch_chunk_count(bp, pr.dks, pr.dvs, r0, len, counts, s));
     HIPCHK(ctx, launch_exclusive_scan(counts, offsets, n, scan_temp, &d_tot->pairs, s));
     void *h = nullptr;
     CHK(pinned_get(ctx, sizeof(Totals), &h));
@@ -395,7 +397,7 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     CHK(ws_get_t(ctx, kPairV1, P, &pv1));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.M * bp.n_clusters))),
                &sort_temp));
-    HIPCHK(ctx, launch_chunk_emit(bp, pr.mean2d, pr.ext, pr.dks, pr.dvs, r0, len, counts, offsets, pk0, pv0, s));
+    HIPCHK(ctx, launch_chunk_emit(bp, pr.dks, pr.dvs, r0, len, offsets, P, pk0, pv0, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStKeygen, e0, e1);
     bool palt = false;
@@ -639,6 +641,8 @@ lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lf
         return fail(ctx, LFR_ERR_INVALID_ARG, "rational parameters need den > 0 and pitch > 0");
     if (!tile_ok(D.tile_w) || !tile_ok(D.tile_h))
         return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: each side must be 8, 16 or 32", D.tile_w, D.tile_h);
+    if ((D.width + D.tile_w - 1) / D.tile_w > 65535 || (D.height + D.tile_h - 1) / D.tile_h > 65535)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
     // Exact-integer form of Eq. 1-3; every intermediate must fit in int64.
     typedef __int128 i128;
     auto g = [](i128 a, i128 b) {
@@ -684,6 +688,8 @@ lfr_status lfr_display_create_from_map(lfr_context *ctx, int32_t W, int32_t H, i
     if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || N < 1 || N > 65535)
         return fail(ctx, LFR_ERR_INVALID_ARG, "bad panel or view count");
     if (!tile_ok(tw) || !tile_ok(th)) return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+    if ((W + tw - 1) / tw > 65535 || (H + th - 1) / th > 65535)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
     const size_t n = 3 * (size_t)W * H;
     std::vector<uint16_t> v16(n);
     for (size_t s = 0; s < n; ++s) {
@@ -843,7 +849,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
         CHK(ws_get_t(ctx, kWork, 2, &bp.work));
         HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, s));
     }
-    const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits);
+    const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits, pr.items);
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
     int64_t r0 = 0, len = opts->first_chunk > 0
@@ -944,7 +950,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * d->TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * d->TY * words, s));
-        const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits);
+        const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits, pr.items);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;

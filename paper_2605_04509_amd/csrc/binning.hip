@@ -18,207 +18,152 @@
 
 namespace lfr {
 
-struct TileRect {
-    int x0, x1, y0, y1;  // inclusive tile ranges
-};
-
-// Box of one view in tile coordinates; false if it misses the panel.
-__device__ inline bool view_rect(float2 m, float2 e, const BinParams &bp, TileRect &r)
+// Units of an item: (tile row, 32-tile word) cells of its bounding box.
+__device__ inline int item_units(const ItemRec &r)
 {
-    // pixel x is covered when |x + 0.5 - mx| <= ex
-    const float fx0 = fmaxf(ceilf(m.x - e.x - 0.5f), 0.0f);
-    const float fx1 = fminf(floorf(m.x + e.x - 0.5f), (float)(bp.W - 1));
-    const float fy0 = fmaxf(ceilf(m.y - e.y - 0.5f), 0.0f);
-    const float fy1 = fminf(floorf(m.y + e.y - 0.5f), (float)(bp.H - 1));
-    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
-    r.x0 = (int)fx0 / bp.tw;
-    r.x1 = (int)fx1 / bp.tw;
-    r.y0 = (int)fy0 / bp.th;
-    r.y1 = (int)fy1 / bp.th;
-    return true;
+    if (r.nv == 0) return 0;
+    return ((int)r.bbox.w - (int)r.bbox.z + 1) * (((int)r.bbox.y >> 5) - ((int)r.bbox.x >> 5) + 1);
 }
 
-// The boxes of one (Gaussian, cluster) item: up to kRegViews kept in
-// registers; items with more views recompute their boxes from the means.
-constexpr int kRegViews = 4;
-struct Item {
-    int k = 0;
-    uint32_t i = 0;
-    float2 e = make_float2(0.f, 0.f);
-    int nv = 0;          // views of the cluster (boxes possibly empty)
-    int ylo = 1, yhi = 0, wlo = 1, whi = 0;  // tile-row and 32-tile-word bounds of the union
-    TileRect r[kRegViews];
-    bool ok[kRegViews];
-};
-
-__device__ inline bool item_rect(const BinParams &bp, const float2 *mean2d, const Item &it, int v, TileRect &r)
+// Tiles of the item in unit u: the OR of its views' boxes (or its bounding
+// box when it has more boxes than the record holds) in that row and word,
+// restricted to alive lists.  Also returns the unit's row and word.
+__device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &r, int u, int &ty, int &w)
 {
-    if (v < kRegViews) {
-        r = it.r[v];
-        return it.ok[v];
-    }
-    const float2 m = mean2d[(int64_t)bp.cv_list[bp.cv_off[it.k] + v] * bp.M + it.i];
-    return !isnan(m.x) && view_rect(m, it.e, bp, r);
-}
-
-__device__ inline void item_init(const BinParams &bp, const float2 *mean2d, const float2 *ext, int k, uint32_t i,
-                                 Item &it)
-{
-    it.k = k;
-    it.i = i;
-    it.e = ext[(int64_t)k * bp.M + i];
-    it.nv = bp.cv_off[k + 1] - bp.cv_off[k];
-    int ylo = 1 << 30, yhi = -1, xlo = 1 << 30, xhi = -1;
-    for (int v = 0; v < it.nv; ++v) {
-        const float2 m = mean2d[(int64_t)bp.cv_list[bp.cv_off[k] + v] * bp.M + i];
-        TileRect r;
-        const bool ok = !isnan(m.x) && view_rect(m, it.e, bp, r);
-        if (v < kRegViews) {
-            it.r[v] = r;
-            it.ok[v] = ok;
-        }
-        if (ok) {
-            ylo = min(ylo, r.y0);
-            yhi = max(yhi, r.y1);
-            xlo = min(xlo, r.x0);
-            xhi = max(xhi, r.x1);
-        }
-    }
-    it.ylo = ylo;
-    it.yhi = yhi;
-    it.wlo = xlo >> 5;
-    it.whi = xhi >= 0 ? (xhi >> 5) : -1;
-}
-
-__device__ inline int item_units(const Item &it)
-{
-    return it.yhi < it.ylo ? 0 : (it.yhi - it.ylo + 1) * (it.whi - it.wlo + 1);
-}
-
-// Alive tiles of the union in one (tile row, 32-tile word) unit: OR of the
-// views' interval masks, AND the list-alive bits.
-__device__ inline uint32_t unit_mask(const BinParams &bp, const float2 *mean2d, const Item &it, int u)
-{
-    const int nw = it.whi - it.wlo + 1;
-    const int ty = it.ylo + u / nw;
-    const int w = it.wlo + u % nw;
+    const int w0 = (int)r.bbox.x >> 5;
+    const int nw = ((int)r.bbox.y >> 5) - w0 + 1;
+    ty = (int)r.bbox.z + u / nw;
+    w = w0 + u % nw;
+    const int xb = w << 5;
     uint32_t m = 0;
-    for (int v = 0; v < it.nv; ++v) {
-        TileRect r;
-        if (!item_rect(bp, mean2d, it, v, r) || ty < r.y0 || ty > r.y1) continue;
-        const int lo = r.x0 - (w << 5), hi = r.x1 - (w << 5);
+    const int nb = r.flags ? 1 : (int)r.nv;
+    for (int v = 0; v < nb; ++v) {
+        const ushort4 b = r.flags ? r.bbox : r.r[v];
+        if (ty < (int)b.z || ty > (int)b.w) continue;
+        const int lo = (int)b.x - xb, hi = (int)b.y - xb;
         if (hi < 0 || lo > 31) continue;
         const uint32_t mh = hi >= 31 ? 0xFFFFFFFFu : ((2u << hi) - 1u);
         const uint32_t ml = lo <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << lo);
         m |= mh & ml;
     }
-    const uint32_t *alive_k = bp.alive + (int64_t)it.k * bp.TY * bp.alive_words;
+    const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;
     return m & alive_k[(int64_t)ty * bp.alive_words + w];
 }
 
-__device__ inline void unit_emit(const BinParams &bp, const Item &it, int u, uint32_t m, uint32_t *keys,
-                                 uint32_t *vals)
+// Position of the k-th set bit of m (k < popcount(m)).
+__device__ inline int select_bit(uint32_t m, int k)
 {
-    const int nw = it.whi - it.wlo + 1;
-    const int ty = it.ylo + u / nw;
-    const int w = it.wlo + u % nw;
-    const uint32_t base = (uint32_t)ty * (uint32_t)bp.TX + ((uint32_t)w << 5);
-    int n = 0;
-    while (m) {
-        const int b = __ffs(m) - 1;
-        m &= m - 1u;
-        keys[n] = ((base + (uint32_t)b) << bp.cluster_bits) | (uint32_t)it.k;
-        vals[n] = it.i;
-        ++n;
-    }
+    int pos = 0, c;
+    c = __popc(m & 0xFFFFu);
+    if (k >= c) { k -= c; m >>= 16; pos += 16; }
+    c = __popc(m & 0xFFu);
+    if (k >= c) { k -= c; m >>= 8; pos += 8; }
+    c = __popc(m & 0xFu);
+    if (k >= c) { k -= c; m >>= 4; pos += 4; }
+    c = __popc(m & 0x3u);
+    if (k >= c) { k -= c; m >>= 2; pos += 2; }
+    if (k >= (int)(m & 1u)) pos += 1;
+    return pos;
 }
 
-// Items with at most this many (row, word) units are handled by their own
-// lane; larger ones by the whole wavefront, one at a time.
-constexpr int kLaneUnits = 6;
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Largest lane l with key[l] <= x, for a key that is non-decreasing over the
+// lanes and key[0] <= x.
+__device__ inline int wave_search(uint32_t key, uint32_t x)
+{
+    int l = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if ((uint32_t)__shfl((int)key, l + step, 64) <= x) l += step;
+    return l;
+}
 
 // Items of one chunk: depth ranks [r0, r0 + len) of every cluster; item
 // (k, r) sits at k * M + r of the depth-sorted arrays and at k * len + (r - r0)
-// of the chunk's count / offset arrays.  The order of pairs inside one item
-// is irrelevant (each tile appears at most once per item), so cooperative
-// emission may place them in any order within the item's slot range.
+// of the chunk's count / offset arrays.
+//
+// Load balancing: each wavefront enumerates the units of its 64 consecutive
+// items in item order and hands them out 64 at a time, so an item covering
+// thousands of tiles is spread over the whole wavefront.  The counting pass
+// adds each unit's tile count to its item (LDS); the emitting pass lays the
+// wavefront's pairs out contiguously (its items' offsets are consecutive)
+// and writes them with consecutive lanes on consecutive slots.
 template <bool kEmit>
-__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const float2 *__restrict__ mean2d,
-                                                           const float2 *__restrict__ ext,
-                                                           const uint64_t *__restrict__ dkey_sorted,
+__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const uint64_t *__restrict__ dkey_sorted,
                                                            const uint32_t *__restrict__ dval_sorted, int64_t r0,
                                                            int64_t len, uint32_t *__restrict__ counts,
-                                                           const uint32_t *__restrict__ offsets,
+                                                           const uint32_t *__restrict__ offsets, uint64_t n_pairs,
                                                            uint32_t *__restrict__ pair_keys,
                                                            uint32_t *__restrict__ pair_vals)
 {
+    __shared__ uint32_t s_cnt[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t rl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
-    const int lane = threadIdx.x & 63;
     const bool in = rl < len;
     const int64_t o = (int64_t)k * len + rl;
-    Item it;
-    bool valid = false;
+    const ItemRec *items_k = bp.items + (int64_t)k * bp.M;
+    uint32_t i = 0;
+    int U = 0;
     if (in) {
         const int64_t e = (int64_t)k * bp.M + r0 + rl;
-        valid = (uint32_t)dkey_sorted[e] != 0xFFFFFFFFu;
-        if (valid) item_init(bp, mean2d, ext, k, dval_sorted[e], it);
-    }
-    const int units = valid ? item_units(it) : 0;
-    const bool big = units > kLaneUnits;
-    uint32_t cnt = 0;
-    uint32_t off = 0, limit = 0;
-    if (kEmit && valid) {
-        off = offsets[o];
-        limit = counts[o];
-    }
-    if (valid && !big) {
-        for (int u = 0; u < units; ++u) {
-            const uint32_t m = unit_mask(bp, mean2d, it, u);
-            if (kEmit && m) {
-                // bounded by the count pass, so the pair buffer is never overrun
-                if (cnt + (uint32_t)__popc(m) <= limit) unit_emit(bp, it, u, m, pair_keys + off + cnt, pair_vals + off + cnt);
-            }
-            cnt += (uint32_t)__popc(m);
+        if ((uint32_t)dkey_sorted[e] != 0xFFFFFFFFu) {
+            i = dval_sorted[e];
+            U = item_units(items_k[i]);
         }
     }
-    // large items: the whole wavefront walks one item's units at a time
-    uint64_t todo = __ballot(big);
-    while (todo) {
-        const int src = __ffsll((long long)todo) - 1;
-        todo &= todo - 1ull;
-        Item w;
-        w.k = k;
-        w.i = (uint32_t)__shfl((int)it.i, src, 64);
-        item_init(bp, mean2d, ext, k, w.i, w);
-        const int wu = item_units(w);
-        const uint32_t woff = (uint32_t)__shfl((int)off, src, 64);
-        const uint32_t wlimit = (uint32_t)__shfl((int)limit, src, 64);
-        uint32_t total = 0;  // running count of the units before this round
-        for (int ub = 0; ub < wu; ub += 64) {
-            const int u = ub + lane;
-            const uint32_t m = u < wu ? unit_mask(bp, mean2d, w, u) : 0u;
-            const uint32_t c = (uint32_t)__popc(m);
-            if (kEmit) {
-                uint32_t incl = c;  // inclusive scan of c over the wavefront
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
-                    if (lane >= d) incl += t;
+    const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);
+    const uint32_t ubase = uincl - (uint32_t)U;
+    const uint32_t utot = (uint32_t)__shfl((int)uincl, 63, 64);
+    if (!kEmit) s_cnt[wave][lane] = 0;
+    uint64_t out = 0;  // next pair slot of this wavefront
+    if (kEmit && utot > 0) out = (uint64_t)offsets[(int64_t)k * len + (rl - lane)];
+    for (uint32_t ub = 0; ub < utot; ub += 64) {
+        const uint32_t u = ub + (uint32_t)lane;
+        const bool has = u < utot;
+        const int owner = wave_search(ubase, has ? u : utot - 1);
+        const uint32_t iown = (uint32_t)__shfl((int)i, owner, 64);
+        const uint32_t uloc = (has ? u : utot - 1) - (uint32_t)__shfl((int)ubase, owner, 64);
+        int ty = 0, w = 0;
+        uint32_t m = 0;
+        if (has) m = unit_mask(bp, k, items_k[iown], (int)uloc, ty, w);
+        const uint32_t c = (uint32_t)__popc(m);
+        if (!kEmit) {
+            if (c) atomicAdd(&s_cnt[wave][owner], c);
+        } else {
+            // spread this round's pairs over the lanes
+            const uint32_t cincl = wave_incl_scan(c, lane);
+            const uint32_t cbase = cincl - c;
+            const uint32_t ctot = (uint32_t)__shfl((int)cincl, 63, 64);
+            const uint32_t tilebase = (uint32_t)ty * (uint32_t)bp.TX + ((uint32_t)w << 5);
+            for (uint32_t pb = 0; pb < ctot; pb += 64) {
+                const uint32_t pidx = pb + (uint32_t)lane;
+                const uint32_t px = pidx < ctot ? pidx : ctot - 1;
+                const int q = wave_search(cbase, px);
+                const uint32_t mq = (uint32_t)__shfl((int)m, q, 64);
+                const uint32_t kth = px - (uint32_t)__shfl((int)cbase, q, 64);
+                const uint32_t tb = (uint32_t)__shfl((int)tilebase, q, 64);
+                const uint32_t iq = (uint32_t)__shfl((int)iown, q, 64);
+                const uint64_t slot = out + pidx;
+                if (pidx < ctot && slot < n_pairs) {
+                    const uint32_t t = tb + (uint32_t)select_bit(mq, (int)kth);
+                    pair_keys[slot] = (t << bp.cluster_bits) | (uint32_t)k;
+                    pair_vals[slot] = iq;
                 }
-                const uint32_t at = total + incl - c;
-                if (c && at + c <= wlimit) unit_emit(bp, w, u, m, pair_keys + woff + at, pair_vals + woff + at);
-                total += (uint32_t)__shfl((int)incl, 63, 64);
-            } else {
-                uint32_t sum = c;
-#pragma unroll
-                for (int d = 32; d > 0; d >>= 1) sum += (uint32_t)__shfl_xor((int)sum, d, 64);
-                total += sum;
             }
+            out += ctot;
         }
-        if (lane == src) cnt = total;
     }
-    if (!kEmit && in) counts[o] = valid ? cnt : 0u;
+    if (!kEmit && in) counts[o] = s_cnt[wave][lane];
 }
 
 __global__ void __launch_bounds__(256) fill_kernel(uint32_t *p, uint32_t v, int64_t n)
@@ -262,25 +207,24 @@ __global__ void __launch_bounds__(256) alive_bits_kernel(const uint32_t *__restr
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_chunk_count(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                              const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0, int64_t len,
-                              uint32_t *counts, hipStream_t s)
+hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                              int64_t r0, int64_t len, uint32_t *counts, hipStream_t s)
 {
     if (len == 0 || bp.n_clusters == 0) return hipSuccess;
-    hipLaunchKernelGGL(chunk_tiles_kernel<false>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp, mean2d,
-                       ext, dkey_sorted, dval_sorted, r0, len, counts, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (uint32_t *)nullptr);
+    hipLaunchKernelGGL(chunk_tiles_kernel<false>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp,
+                       dkey_sorted, dval_sorted, r0, len, counts, (const uint32_t *)nullptr, (uint64_t)0,
+                       (uint32_t *)nullptr, (uint32_t *)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_emit(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                             const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0, int64_t len,
-                             uint32_t *counts, const uint32_t *offsets, uint32_t *pair_keys, uint32_t *pair_vals,
-                             hipStream_t s)
+hipError_t launch_chunk_emit(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                             int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs, uint32_t *pair_keys,
+                             uint32_t *pair_vals, hipStream_t s)
 {
-    if (len == 0 || bp.n_clusters == 0) return hipSuccess;
-    hipLaunchKernelGGL(chunk_tiles_kernel<true>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp, mean2d,
-                       ext, dkey_sorted, dval_sorted, r0, len, counts, offsets, pair_keys, pair_vals);
+    if (len == 0 || bp.n_clusters == 0 || n_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(chunk_tiles_kernel<true>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp,
+                       dkey_sorted, dval_sorted, r0, len, (uint32_t *)nullptr, offsets, n_pairs, pair_keys,
+                       pair_vals);
     return hipGetLastError();
 }
 

@@ -147,6 +147,21 @@ hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_
                             int W, int H, int tw, int th, const uint32_t *offsets, Task *tasks,
                             hipStream_t s);
 
+// Per (cluster, Gaussian) binning record, written by the projection: the
+// tile boxes of the Gaussian in each of the cluster's views (boxes in tile
+// units, inclusive; up to kItemViews non-empty boxes) and their union's
+// bounding box.  With more non-empty boxes than fit, `flags` bit 0 is set and
+// binning uses the bounding box (still a conservative cover).  64 B aligned.
+constexpr int kItemViews = 6;
+struct alignas(64) ItemRec {
+    uint32_t i;
+    uint16_t nv;
+    uint16_t flags;
+    ushort4 bbox;              // x0, x1, y0, y1
+    ushort4 r[kItemViews];     // x0, x1, y0, y1 per non-empty view box
+};
+static_assert(sizeof(ItemRec) == 64, "ItemRec must be 64 bytes");
+
 struct SceneDev {
     int64_t M;
     int32_t deg;
@@ -154,12 +169,17 @@ struct SceneDev {
 };
 struct ProjectOut {
     GaussRec *rec;      // [K'][M]
-    float2 *ext;        // [K'][M]  conservative half extents (pixels)
+    ItemRec *items;     // [K'][M]  tile boxes per cluster view
     uint64_t *dkey;     // [K'][M]  (cluster << 32) | depth bits, 0xFFFFFFFF if invalid
     uint32_t *dval;     // [K'][M]  Gaussian index
     float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
 };
-hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, int W, int H,
+struct TileGrid {
+    int W, H, tw, th;
+    const int32_t *cv_off;   // [K'+1] views of each cluster ...
+    const int32_t *cv_list;  // ... as view slots
+};
+hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileGrid &tg,
                           int n_clusters, const int32_t *cluster_cam, int n_views,
                           const int32_t *view_cam, const ProjectOut &out, hipStream_t s);
 hipError_t launch_project_records(const SceneDev &sc, const DevCamera *cam, int W, int H,
@@ -190,14 +210,13 @@ struct BinParams {
     const int32_t *cv_list;   // compact view slots
     const uint32_t *alive;    // [K'][TY][alive_words] bit per (cluster, tile) list still needed
     int alive_words;          // 32-bit words per tile row
+    const ItemRec *items;     // [K'][M]
 };
-hipError_t launch_chunk_count(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                              const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0,
-                              int64_t len, uint32_t *counts, hipStream_t s);
-hipError_t launch_chunk_emit(const BinParams &bp, const float2 *mean2d, const float2 *ext,
-                             const uint64_t *dkey_sorted, const uint32_t *dval_sorted, int64_t r0,
-                             int64_t len, uint32_t *counts, const uint32_t *offsets, uint32_t *pair_keys,
-                             uint32_t *pair_vals, hipStream_t s);
+hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                              int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
+hipError_t launch_chunk_emit(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+                             int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs,
+                             uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s);
 hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,

@@ -235,8 +235,23 @@ __device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, 
     g.finite = fin;
 }
 
+// Tile box (inclusive tile ranges) of the pixels whose centres lie within
+// the half extents e of mean m; false if it misses the panel.
+__device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 &b)
+{
+    // pixel x is covered when |x + 0.5 - mx| <= ex
+    const float fx0 = fmaxf(ceilf(m.x - e.x - 0.5f), 0.0f);
+    const float fx1 = fminf(floorf(m.x + e.x - 0.5f), (float)(tg.W - 1));
+    const float fy0 = fmaxf(ceilf(m.y - e.y - 0.5f), 0.0f);
+    const float fy1 = fminf(floorf(m.y + e.y - 0.5f), (float)(tg.H - 1));
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
+    b = make_ushort4((unsigned short)((int)fx0 / tg.tw), (unsigned short)((int)fx1 / tg.tw),
+                     (unsigned short)((int)fy0 / tg.th), (unsigned short)((int)fy1 / tg.th));
+    return true;
+}
+
 template <int DEG>
-__global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams,
+__global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
                                                       int n_clusters, const int32_t *__restrict__ cluster_cam,
                                                       int n_views, const int32_t *__restrict__ view_cam,
                                                       ProjectOut out)
@@ -272,7 +287,28 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
             r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
             r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
             out.rec[idx] = r;
-            out.ext[idx] = f.ext;
+            // tile boxes of the cluster's views: this Gaussian's mean in each
+            // view (the same values the per-view mean planes hold) with the
+            // cluster's extents
+            ItemRec it;
+            it.i = (uint32_t)i;
+            it.nv = 0;
+            it.flags = 0;
+            unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
+            for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
+                const MeanProj mv = project_mean(cams[view_cam[tg.cv_list[v]]], mx, my, mz, g.finite);
+                ushort4 b;
+                if (!mv.valid || !tile_box(mv.m2d, f.ext, tg, b)) continue;
+                if (it.nv < kItemViews) it.r[it.nv++] = b;
+                else it.flags = 1;
+                x0 = min(x0, b.x);
+                x1 = max(x1, b.y);
+                y0 = min(y0, b.z);
+                y1 = max(y1, b.w);
+            }
+            it.bbox = make_ushort4(x0, x1, y0, y1);
+            for (int q = it.nv; q < kItemViews; ++q) it.r[q] = make_ushort4(1, 0, 1, 0);
+            out.items[idx] = it;
             out.dkey[idx] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(m.depth);
         } else {
             out.dkey[idx] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
@@ -315,19 +351,17 @@ __global__ void __launch_bounds__(256) project_records_kernel(SceneDev sc, const
     out[i] = r;
 }
 
-hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, int W, int H, int n_clusters,
+hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileGrid &tg, int n_clusters,
                           const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
                           const ProjectOut &out, hipStream_t s)
 {
-    (void)W;
-    (void)H;
     if (sc.M == 0) return hipSuccess;
     const dim3 grid((unsigned)((sc.M + 255) / 256)), block(256);
     switch (sc.deg) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    default: hipLaunchKernelGGL(project_kernel<3>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
     }
     return hipGetLastError();
 }
