@@ -59,7 +59,12 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 // One 64-lane wavefront per task: up to 64 subpixels of one tile and one
 // cluster, in Psi order.  Gaussians of the (tile, cluster) list are staged
 // 64 at a time into LDS (record + the mean for each distinct view of the
-// wavefront), then every lane walks the batch.
+// wavefront; the next batch is fetched into registers while the current one
+// is evaluated), then every lane walks the batch.  The walk is branch-free:
+// a lane that has stopped keeps executing with its updates masked by selects,
+// and the wavefront leaves as soon as all of its lanes have stopped (checked
+// every 16 Gaussians).  Batches are padded to a multiple of 4 with
+// zero-opacity entries, whose alpha is 0 and never passes the cutoff.
 template <bool kCount>
 __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
                                                           int n_tasks, int per)
@@ -101,32 +106,58 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     const bool was_done = done;
     unsigned long long n_eval = 0, n_blend = 0;
     __syncthreads();
-    if (__ballot(!done) != 0) {
+    int slots[kMaxWaveViews];
+#pragma unroll
+    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = q < n_runs ? s_slot[q] : 0;
+
+    // registers holding the batch being fetched
+    float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gc = ga;
+    float2 gm[kMaxWaveViews];
+    auto fetch = [&](uint32_t base) {
+        const uint32_t e = base + (uint32_t)lane;
+        ga = make_float4(0.f, 0.f, 0.f, 0.f);
+        gc = ga;
+#pragma unroll
+        for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = make_float2(0.f, 0.f);
+        if (e < range.y) {
+            const uint32_t i = bp.vals[e];
+            const GaussRec g = rec[i];
+            ga = g.a;
+            gc = g.c;
+#pragma unroll
+            for (int q = 0; q < kMaxWaveViews; ++q)
+                if (q < n_runs) gm[q] = sanitize_mean(bp.mean2d[(int64_t)slots[q] * bp.M + i]);
+        }
+    };
+    if (__ballot(!done) != 0 && range.x < range.y) {
+        fetch(range.x);
         for (uint32_t base = range.x; base < range.y; base += kWave) {
-            const int nb = (int)min((uint32_t)kWave, range.y - base);
-            if (lane < nb) {
-                const uint32_t i = bp.vals[base + lane];
-                const GaussRec g = rec[i];
-                s_a[lane] = g.a;
-                *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
-                for (int q = 0; q < n_runs; ++q)
-                    s_mu[q][lane] = sanitize_mean(bp.mean2d[(int64_t)s_slot[q] * bp.M + i]);
-            }
+            s_a[lane] = ga;
+            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = gc;
+#pragma unroll
+            for (int q = 0; q < kMaxWaveViews; ++q)
+                if (q < n_runs) s_mu[q][lane] = gm[q];
             __syncthreads();
-            if (!done) {
-                for (int g = 0; g < nb; ++g) {
+            if (base + kWave < range.y) fetch(base + kWave);
+            const int nb = (int)min((uint32_t)kWave, range.y - base);
+            const int nb4 = (nb + 3) & ~3;
+            for (int g0 = 0; g0 < nb4; g0 += 16) {
+                const int g1 = min(g0 + 16, nb4);
+#pragma unroll 4
+                for (int g = g0; g < g1; ++g) {
                     const float alpha = step_alpha(s_a[g], s_mu[my_run][g], px, py);
-                    if (kCount) ++n_eval;
-                    if (alpha < kAlphaMin) continue;
                     const float Tn = T * (1.0f - alpha);
-                    if (Tn < kTStop) {
-                        done = true;
-                        break;
+                    const bool pass = !done && alpha >= kAlphaMin;
+                    const bool take = pass && Tn >= kTStop;
+                    if (kCount) {
+                        n_eval += (!done && g < nb) ? 1u : 0u;
+                        n_blend += take ? 1u : 0u;
                     }
-                    C = fmaf(s_c[g * 4 + u] * alpha, T, C);
-                    T = Tn;
-                    if (kCount) ++n_blend;
+                    C = take ? fmaf(s_c[g * 4 + u] * alpha, T, C) : C;
+                    T = take ? Tn : T;
+                    done = done || (pass && !take);
                 }
+                if (__ballot(!done) == 0) break;
             }
             if (__ballot(!done) == 0) break;
             __syncthreads();
