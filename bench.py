@@ -117,11 +117,15 @@ def main():
     cams_np = pack_cameras(w.cameras())
     cams = lfr.cameras_array(cams_np)
     ctx = lfr.Context(0)
-    disp = lfr.Display(ctx, w.display)
     ds = lfr.DeviceScene.from_numpy(scene, device="cuda:0")
     out = torch.empty((w.display.height, w.display.width, 3), dtype=torch.float32, device="cuda:0")
     sync = torch.cuda.synchronize
     S = args.cluster_size
+    # tile shape: the image does not depend on it, so pick the fastest (untimed)
+    best, tune = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(S,), reps=2)
+    log("autotune", best)
+    params = w.display.with_tile(best["tile_w"], best["tile_h"])
+    disp = lfr.Display(ctx, params)
 
     def frame(cs=S, remap=True, timing=False):
         lfr.render(ctx, disp, ds, cams, cluster_size=cs, remap=remap, timing=timing, out=out)
@@ -162,7 +166,7 @@ def main():
     blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
     # tile sort: every chunk's pairs pass through ceil(tile_bits / 8) scatter
     # launches, each reading and writing (key, value) = 16 B per pair
-    d = w.display
+    d = params
     n_tiles = -(-d.width // d.tile_w) * -(-d.height // d.tile_h)
     passes = -(-max(1, (n_tiles - 1).bit_length()) // 8)
     launches = max(scatter_launches / args.steps, 1.0)
@@ -183,44 +187,55 @@ def main():
         "config": {"workload": (f"{w.name}: {scene.num_gaussians} Gaussians (SH{scene.sh_degree}), "
                                 f"{w.display.num_views} views over {w.span_deg:g} deg, "
                                 f"{w.display.width}x{w.display.height}, slant {w.display.tan_slant.num}/"
-                                f"{w.display.tan_slant.den}, pitch {w.display.pitch.num}/{w.display.pitch.den}, "
-                                f"tile {w.display.tile_w}x{w.display.tile_h}"),
-                   "cluster_size": S, "remap": True, "parallelism": "single GPU"},
+                                f"{w.display.tan_slant.den}, pitch {w.display.pitch.num}/{w.display.pitch.den}"),
+                   "cluster_size": S, "remap": True, "tile": [params.tile_w, params.tile_h],
+                   "parallelism": "single GPU"},
+        "autotune": tune,
         "stages_ms": stages, "pairs": work["pairs"], "chunks": work["chunks"], "clusters": work["clusters"],
         "views": work["views"],
         "roofline": roofline, "roofline_other": other, "fwd_bwd_ms": None,
     }
 
     if not args.no_ablation:
+        # the paper's ablation modes, each on its own fastest tile shape
         modes = {}
         for name, cs, rm in (("reuse_only", S, False), ("remap_only", 1, True), ("neither", 1, False)):
-            frame(cs, rm)
-            t = timed(lambda: frame(cs, rm), 3, sync)
-            modes[name] = {"cluster_size": cs, "remap": rm, "frames_per_s": 1.0 / t, "ms": t * 1e3}
+            b, _ = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(cs,), reps=1, remap=rm,
+                                tiles=((16, 16), (32, 16), (32, 32), (32, 64)))
+            dm = lfr.Display(ctx, w.display.with_tile(b["tile_w"], b["tile_h"]))
+            run = lambda: lfr.render(ctx, dm, ds, cams, cluster_size=cs, remap=rm, out=out)
+            run()
+            t = timed(run, 3, sync)
+            modes[name] = {"cluster_size": cs, "remap": rm, "tile": [b["tile_w"], b["tile_h"]],
+                           "frames_per_s": 1.0 / t, "ms": t * 1e3}
+            dm.close()
             log(name, modes[name])
-        modes["reuse+remap"] = {"cluster_size": S, "remap": True, "frames_per_s": fps, "ms": sec * 1e3}
+        modes["reuse+remap"] = {"cluster_size": S, "remap": True, "tile": [params.tile_w, params.tile_h],
+                                "frames_per_s": fps, "ms": sec * 1e3}
         result["modes"] = modes
 
     if not args.no_plain:
         plain = {}
         for label, cull in (("all_views", False), ("referenced_views", True)):
-            best = None
-            for vb in (5, 10, 20):
-                def pf(vb=vb, cull=cull):
-                    lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out)
-                try:
-                    pf()
-                except lfr.LfrError as e:         # e.g. more pairs than 32-bit offsets hold
-                    log(f"plain {label} batch {vb}: {e}")
-                    continue
-                t = timed(pf, 1, sync)
-                log(f"plain {label} batch {vb}: {t * 1e3:.1f} ms")
-                if best is None or t < best[1]:
-                    best = (vb, t)
-            vb = best[0]
-            t = timed(lambda: lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out),
-                      args.plain_steps, sync)
-            plain[label] = {"view_batch": vb, "frames_per_s": 1.0 / t, "ms": t * 1e3}
+            best_p = None
+            for tile in (16, 32):
+                for vb in (10, 20):
+                    def pf(vb=vb, cull=cull, tile=tile):
+                        lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out,
+                                                       tile=tile)
+                    try:
+                        pf()
+                    except lfr.LfrError as e:         # e.g. more pairs than 32-bit offsets hold
+                        log(f"plain {label} tile {tile} batch {vb}: {e}")
+                        continue
+                    t = timed(pf, 1, sync)
+                    log(f"plain {label} tile {tile} batch {vb}: {t * 1e3:.1f} ms")
+                    if best_p is None or t < best_p[2]:
+                        best_p = (vb, tile, t)
+            vb, tile = best_p[0], best_p[1]
+            t = timed(lambda: lfr.render_fullframe_interlace(ctx, disp, ds, cams, view_batch=vb, cull=cull, out=out,
+                                                             tile=tile), args.plain_steps, sync)
+            plain[label] = {"view_batch": vb, "tile": tile, "frames_per_s": 1.0 / t, "ms": t * 1e3}
         result["plain"] = plain
         result["speedup_vs_plain"] = fps / plain["all_views"]["frames_per_s"]
         result["speedup_vs_plain_referenced"] = fps / plain["referenced_views"]["frames_per_s"]

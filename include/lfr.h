@@ -60,7 +60,8 @@ typedef struct { int64_t num, den; } lfr_rational;
 /* Display description (section 3.1).  width/height in pixels (>= 1; three
  * subpixels per pixel), num_views N in [1, 65535], tan_slant = tan(alpha),
  * pitch = L_x in subpixels (> 0), offset = K_offset in subpixels, tile size
- * in pixels (each of tile_w, tile_h in {8, 16, 32}). */
+ * in pixels (tile_w, tile_h in {8, 16, 32, 64}, tile_w * tile_h <= 2048).
+ * The tile shape changes only the amount of work, never the image. */
 typedef struct {
     int32_t width, height, num_views;
     lfr_rational tan_slant, pitch, offset;
@@ -104,6 +105,9 @@ typedef struct {
                                later chunks grow 4x; 0 = max(4096, M/256).
                                Changes only the amount of work, never the
                                image.                                       */
+    int32_t fullframe_tile; /* lfr_render_fullframe_interlace only: square
+                               tile side of the per-view rasterizer, one of
+                               8, 16, 32 (0 = 16)                           */
 } lfr_render_opts;
 
 /* Counters and timings of the last render on a context. */
@@ -204,6 +208,30 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
  * num_gaussians lfr_proj_record entries (caller-owned device memory). */
 lfr_status lfr_project(lfr_context *ctx, const lfr_scene *scene, const lfr_camera *host_cam,
                        int32_t width, int32_t height, lfr_proj_record *out_device);
+
+/* ---- autotuning ------------------------------------------------------------- */
+
+typedef struct {
+    int32_t tile_w, tile_h;   /* display tile shape                         */
+    int32_t cluster_size;     /* S                                          */
+    float ms;                 /* median render time over the timed repetitions */
+    uint64_t pairs;           /* Gaussian-(tile, cluster) pairs of one render */
+} lfr_tune_result;
+
+/* Time lfr_render for every (tile shape, cluster size) candidate and pick the
+ * fastest.  For each tile shape a temporary display is built from `desc`
+ * (its tile fields are replaced); renders use `opts` with cluster_size
+ * replaced; one untimed render precedes `reps` timed ones (HIP events on the
+ * context stream).  tiles: n_tiles (w, h) pairs; sizes: n_sizes cluster
+ * sizes.  out_device: H*W*3 float32 scratch image (caller-owned).
+ * results (host, may be NULL) receives n_tiles * n_sizes entries in
+ * tile-major order; best (host) the fastest.  Tile shape never changes the
+ * image; cluster size does (it sets the reuse approximation), so callers
+ * that need a fixed image pass a single size.  Synchronizes. */
+lfr_status lfr_autotune(lfr_context *ctx, const lfr_display_desc *desc, const lfr_scene *scene,
+                        const lfr_camera *host_cams, int32_t num_cams, const lfr_render_opts *opts,
+                        const int32_t *tiles, int32_t n_tiles, const int32_t *sizes, int32_t n_sizes,
+                        int32_t reps, float *out_device, lfr_tune_result *results, lfr_tune_result *best);
 
 /* ---- device sort (used by the binning stage, exposed for testing) ---------- */
 

@@ -284,9 +284,22 @@ struct Projected {
     int cbits = 0, tbits = 0;
 };
 
-lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_scene *scene, const DevTables &dt,
+// A tile grid over the W x H panel.
+struct Grid {
+    int W, H, tw, th, TX, TY, T;
+};
+Grid make_grid(int W, int H, int tw, int th)
+{
+    Grid g{W, H, tw, th, (W + tw - 1) / tw, (H + th - 1) / th, 0};
+    g.T = g.TX * g.TY;
+    return g;
+}
+Grid grid_of(const lfr_display *d) { return make_grid(d->W, d->H, d->tw, d->th); }
+
+lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *scene, const DevTables &dt,
                             const ViewTables &vt, Projected *out)
 {
+    const Grid *d = &d_;
     hipStream_t s = ctx->stream;
     Timer &tm = ctx->timer;
     const int64_t M = scene->num_gaussians;
@@ -328,9 +341,10 @@ lfr_status project_and_sort(lfr_context *ctx, const lfr_display *d, const lfr_sc
     return LFR_OK;
 }
 
-BinParams bin_params(const lfr_display *d, const DevTables &dt, const ViewTables &vt, int64_t M, int cbits,
+BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int cbits,
                      const uint32_t *alive, const ItemRec *items)
 {
+    const Grid *d = &d_;
     BinParams bp;
     bp.M = M;
     bp.n_clusters = vt.n_clusters;
@@ -485,6 +499,7 @@ lfr_status check_render_args(lfr_context *ctx, const lfr_display *d, const lfr_s
     if (!opts) return fail(ctx, LFR_ERR_INVALID_ARG, "opts is NULL");
     if (opts->cluster_size < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "cluster_size must be >= 1");
     if (opts->first_chunk < 0) return fail(ctx, LFR_ERR_INVALID_ARG, "first_chunk must be >= 0");
+    if (opts->fullframe_tile < 0) return fail(ctx, LFR_ERR_INVALID_ARG, "fullframe_tile must be >= 0");
     if (opts->cluster_size > kMaxClusterViews)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "cluster_size %d > %d", opts->cluster_size, kMaxClusterViews);
     for (float b : opts->background)
@@ -610,7 +625,10 @@ static lfr_status display_finish(lfr_context *ctx, lfr_display *d, lfr_display *
     return LFR_OK;
 }
 
-static bool tile_ok(int t) { return t == 8 || t == 16 || t == 32; }
+// Tile sides 8..64 (powers of two) with at most 2048 pixels per tile (the
+// remap LUT sorts a tile's subpixels in 32 KB of LDS).
+static bool tile_ok(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
+static bool tile_shape_ok(int tw, int th) { return tile_ok(tw) && tile_ok(th) && tw * th <= 2048; }
 
 static lfr_display *new_display(lfr_context *ctx, int W, int H, int N, int tw, int th)
 {
@@ -639,8 +657,9 @@ lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lf
         return fail(ctx, LFR_ERR_INVALID_ARG, "num_views %d not in [1, 65535]", D.num_views);
     if (D.tan_slant.den <= 0 || D.pitch.den <= 0 || D.offset.den <= 0 || D.pitch.num <= 0)
         return fail(ctx, LFR_ERR_INVALID_ARG, "rational parameters need den > 0 and pitch > 0");
-    if (!tile_ok(D.tile_w) || !tile_ok(D.tile_h))
-        return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: each side must be 8, 16 or 32", D.tile_w, D.tile_h);
+    if (!tile_shape_ok(D.tile_w, D.tile_h))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: sides must be 8, 16, 32 or 64, area <= 2048",
+                    D.tile_w, D.tile_h);
     if ((D.width + D.tile_w - 1) / D.tile_w > 65535 || (D.height + D.tile_h - 1) / D.tile_h > 65535)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
     // Exact-integer form of Eq. 1-3; every intermediate must fit in int64.
@@ -687,7 +706,8 @@ lfr_status lfr_display_create_from_map(lfr_context *ctx, int32_t W, int32_t H, i
     *out = nullptr;
     if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || N < 1 || N > 65535)
         return fail(ctx, LFR_ERR_INVALID_ARG, "bad panel or view count");
-    if (!tile_ok(tw) || !tile_ok(th)) return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+    if (!tile_shape_ok(tw, th))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16, 32 or 64, area <= 2048");
     if ((W + tw - 1) / tw > 65535 || (H + th - 1) / th > 65535)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
     const size_t n = 3 * (size_t)W * H;
@@ -804,7 +824,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     DevTables dt;
     CHK(upload_tables(ctx, d, host_cams, vt, &dt));
     Projected pr;
-    CHK(project_and_sort(ctx, d, scene, dt, vt, &pr));
+    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, &pr));
 
     // traversal state: unsaturated subpixels per (tile, cluster) list and in
     // total, the lists' alive bits, per-subpixel (T, C), per-item flags
@@ -849,7 +869,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
         CHK(ws_get_t(ctx, kWork, 2, &bp.work));
         HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, s));
     }
-    const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits, pr.items);
+    const BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.cbits, alive_bits, pr.items);
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
     int64_t r0 = 0, len = opts->first_chunk > 0
@@ -909,6 +929,10 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
     CHK(begin(ctx));
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
     if (view_batch < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "view_batch must be >= 1");
+    const int ft = opts->fullframe_tile ? opts->fullframe_tile : 16;
+    if (ft != 8 && ft != 16 && ft != 32)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "fullframe_tile must be 8, 16 or 32");
+    const Grid fg = make_grid(display->W, display->H, ft, ft);
     lfr_display *d = const_cast<lfr_display *>(display);
     hipStream_t s = ctx->stream;
     const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
@@ -920,7 +944,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
     for (int j = 0; j < d->N; ++j)
         if (!cull || d->ref[j]) views.push_back(j);
     const int64_t nsub = 3ll * d->W * d->H;
-    const int words = (d->TX + 31) / 32;
+    const int words = (fg.TX + 31) / 32;
     const size_t t0 = tm.mark(s);
     uint64_t pairs = 0;
     for (size_t b0 = 0; b0 < views.size(); b0 += (size_t)view_batch) {
@@ -943,14 +967,14 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         DevTables dt;
         CHK(upload_tables(ctx, d, host_cams, vt, &dt));
         Projected pr;
-        CHK(project_and_sort(ctx, d, scene, dt, vt, &pr));
+        CHK(project_and_sort(ctx, fg, scene, dt, vt, &pr));
         // one chunk with every tile of every view alive
         uint32_t *alive_bits;
         Totals *d_tot;
-        CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * d->TY * words, &alive_bits));
+        CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
-        HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * d->TY * words, s));
-        const BinParams bin = bin_params(d, dt, vt, M, pr.cbits, alive_bits, pr.items);
+        HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.cbits, alive_bits, pr.items);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;
@@ -959,10 +983,10 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         FullFrameParams fp;
         fp.W = d->W;
         fp.H = d->H;
-        fp.tw = d->tw;
-        fp.th = d->th;
-        fp.TX = d->TX;
-        fp.TY = d->TY;
+        fp.tw = fg.tw;
+        fp.th = fg.th;
+        fp.TX = fg.TX;
+        fp.TY = fg.TY;
         fp.M = M;
         fp.n_views = B;
         fp.cluster_bits = pr.cbits;
@@ -984,6 +1008,61 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
     ctx->stats.clusters = (int)views.size();
     ctx->stats.workspace_bytes = ws_total(ctx);
     return finish_timing(ctx);
+}
+
+lfr_status lfr_autotune(lfr_context *ctx, const lfr_display_desc *desc, const lfr_scene *scene,
+                        const lfr_camera *host_cams, int32_t num_cams, const lfr_render_opts *opts,
+                        const int32_t *tiles, int32_t n_tiles, const int32_t *sizes, int32_t n_sizes, int32_t reps,
+                        float *out_device, lfr_tune_result *results, lfr_tune_result *best)
+{
+    CHK(begin(ctx));
+    if (!desc || !opts || !tiles || !sizes || !best || n_tiles < 1 || n_sizes < 1 || reps < 1 || reps > 1000)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "bad autotune arguments");
+    for (int a = 0; a < n_tiles; ++a)
+        if (!tile_shape_ok(tiles[2 * a], tiles[2 * a + 1]))
+            return fail(ctx, LFR_ERR_INVALID_ARG, "candidate tile %d x %d not supported", tiles[2 * a],
+                        tiles[2 * a + 1]);
+    for (int b = 0; b < n_sizes; ++b)
+        if (sizes[b] < 1 || sizes[b] > kMaxClusterViews)
+            return fail(ctx, LFR_ERR_INVALID_ARG, "candidate cluster size %d not supported", sizes[b]);
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    lfr_tune_result bestr{0, 0, 0, 3.0e38f, 0};
+    lfr_status st = LFR_OK;
+    for (int a = 0; a < n_tiles && st == LFR_OK; ++a) {
+        lfr_display_desc dd = *desc;
+        dd.tile_w = tiles[2 * a];
+        dd.tile_h = tiles[2 * a + 1];
+        lfr_display *disp = nullptr;
+        st = lfr_display_create(ctx, &dd, &disp);
+        for (int b = 0; b < n_sizes && st == LFR_OK; ++b) {
+            lfr_render_opts o = *opts;
+            o.cluster_size = sizes[b];
+            o.flags &= ~(uint32_t)(LFR_TIMING | LFR_COUNT_WORK);
+            st = lfr_render(ctx, disp, scene, host_cams, num_cams, &o, out_device);
+            const uint64_t pairs = ctx->stats.pairs;
+            std::vector<float> ms(reps);
+            for (int r = 0; r < reps && st == LFR_OK; ++r) {
+                (void)hipEventRecord(e0, s);
+                st = lfr_render(ctx, disp, scene, host_cams, num_cams, &o, out_device);
+                (void)hipEventRecord(e1, s);
+                if (st == LFR_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms[r], e0, e1);
+            }
+            if (st != LFR_OK) break;
+            std::sort(ms.begin(), ms.end());
+            const lfr_tune_result res{dd.tile_w, dd.tile_h, sizes[b], ms[reps / 2], pairs};
+            if (results) results[a * n_sizes + b] = res;
+            if (res.ms < bestr.ms) bestr = res;
+        }
+        if (disp) lfr_display_destroy(disp);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LFR_OK) return st;
+    *best = bestr;
+    return LFR_OK;
 }
 
 lfr_status lfr_project(lfr_context *ctx, const lfr_scene *scene, const lfr_camera *cam, int32_t W, int32_t H,

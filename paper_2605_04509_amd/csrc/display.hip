@@ -86,20 +86,19 @@ __device__ inline uint32_t tile_subpixel(const TileGeom &g, int W, int r)
 }
 
 // Psi for one tile: the tile's subpixels in row-major order (local rank r)
-// stably sorted by V.  Keys (V << 12) | r are unique, so a bitonic sort in
-// LDS yields exactly the stable order.  One 256-thread block per tile.
-constexpr int kRemapMax = 4096;  // >= 3 * 32 * 32
-
+// stably sorted by V.  Keys (V << 13) | r are unique (r < 3 * 64 * 32 <=
+// 8192), so a bitonic sort in LDS yields exactly the stable order.  One
+// 256-thread block per tile; LDS holds next_pow2(3 * tw * th) keys.
 __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, int H, int tw, int th,
                                                     uint32_t *psi)
 {
-    __shared__ uint32_t keys[kRemapMax];
+    extern __shared__ uint32_t keys[];
     const TileGeom g = tile_geom(blockIdx.x, W, H, tw, th);
     const int n = 3 * g.w * g.h;
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
     for (int r = threadIdx.x; r < n2; r += blockDim.x)
-        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 12) | (uint32_t)r) : 0xFFFFFFFFu;
+        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 13) | (uint32_t)r) : 0xFFFFFFFFu;
     __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -118,13 +117,15 @@ __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, in
         }
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x)
-        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0xFFFu));
+        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0x1FFFu));
 }
 
 hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_t *psi, hipStream_t s)
 {
     const int T = ((W + tw - 1) / tw) * ((H + th - 1) / th);
-    hipLaunchKernelGGL(remap_kernel, dim3(T), dim3(256), 0, s, V, W, H, tw, th, psi);
+    int n2 = 1;
+    while (n2 < 3 * tw * th) n2 <<= 1;
+    hipLaunchKernelGGL(remap_kernel, dim3(T), dim3(256), (size_t)n2 * sizeof(uint32_t), s, V, W, H, tw, th, psi);
     return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ class lfr_scene(Structure):
 
 class lfr_render_opts(Structure):
     _fields_ = [("cluster_size", c_int32), ("flags", c_uint32), ("background", c_float * 3),
-                ("first_chunk", c_int32)]
+                ("first_chunk", c_int32), ("fullframe_tile", c_int32)]
 
 
 class lfr_stats(Structure):
@@ -73,6 +73,14 @@ class lfr_stats(Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class lfr_tune_result(Structure):
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cluster_size", c_int32), ("ms", c_float),
+                ("pairs", c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class lfr_proj_record(Structure):
@@ -104,6 +112,9 @@ _SIGS = {
     "lfr_render_fullframe_interlace": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32,
                                                  POINTER(lfr_render_opts), c_int32, _P]),
     "lfr_project": (c_int32, [c_void_p, POINTER(lfr_scene), _P, c_int32, c_int32, _P]),
+    "lfr_autotune": (c_int32, [c_void_p, POINTER(lfr_display_desc), POINTER(lfr_scene), _P, c_int32,
+                               POINTER(lfr_render_opts), _P, c_int32, _P, c_int32, c_int32, _P,
+                               POINTER(lfr_tune_result), POINTER(lfr_tune_result)]),
     "lfr_sort_pairs_u32": (c_int32, [c_void_p, _P, _P, c_int64, c_int32, c_int32]),
     "lfr_sort_pairs_u64": (c_int32, [c_void_p, _P, _P, c_int64, c_int32, c_int32]),
 }
@@ -188,7 +199,9 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
-            library().lfr_context_destroy(self.handle)
+            lib = _lib
+            if lib is not None:          # may already be gone at interpreter exit
+                lib.lfr_context_destroy(self.handle)
             self.handle = None
 
     __del__ = close
@@ -237,7 +250,9 @@ class Display:
 
     def close(self):
         if getattr(self, "handle", None):
-            library().lfr_display_destroy(self.handle)
+            lib = _lib
+            if lib is not None:
+                lib.lfr_display_destroy(self.handle)
             self.handle = None
 
     __del__ = close
@@ -324,7 +339,7 @@ def render(ctx: Context, display: Display, scene: DeviceScene, cams, cluster_siz
     _require_device_f32(out, "out")
     flags = (LFR_REMAP if remap else 0) | (LFR_CULL_UNREFERENCED if cull else 0) | (LFR_TIMING if timing else 0)
     flags |= LFR_COUNT_WORK if count_work else 0
-    opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background), first_chunk)
+    opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background), first_chunk, 0)
     ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
     sc = scene.c_struct()
     _check(library().lfr_render(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca), ctypes.byref(opts),
@@ -333,18 +348,45 @@ def render(ctx: Context, display: Display, scene: DeviceScene, cams, cluster_siz
 
 
 def render_fullframe_interlace(ctx: Context, display: Display, scene: DeviceScene, cams, view_batch=8, cull=True,
-                               timing=False, background=(0.0, 0.0, 0.0), out=None):
+                               timing=False, background=(0.0, 0.0, 0.0), out=None, tile=16):
     torch = _torch()
     if out is None:
         out = torch.zeros((display.height, display.width, 3), dtype=torch.float32, device=scene.means.device)
     _require_device_f32(out, "out")
     flags = (LFR_CULL_UNREFERENCED if cull else 0) | (LFR_TIMING if timing else 0)
-    opts = lfr_render_opts(1, flags, (c_float * 3)(*background), 0)
+    opts = lfr_render_opts(1, flags, (c_float * 3)(*background), 0, tile)
     ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
     sc = scene.c_struct()
     _check(library().lfr_render_fullframe_interlace(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca),
                                                     ctypes.byref(opts), view_batch, _ptr(out)), ctx.handle)
     return out
+
+
+DEFAULT_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64))
+
+
+def autotune(ctx: Context, params, scene: DeviceScene, cams, cluster_sizes=(8,), tiles=DEFAULT_TILES, reps=3,
+             remap=True, cull=True):
+    """Fastest (tile shape, cluster size) for this scene/display (lfr_autotune).
+    Returns (best, all_results) as dicts."""
+    import numpy as np
+    torch = _torch()
+    p = params
+    desc = lfr_display_desc(p.width, p.height, p.num_views, _rat(p.tan_slant), _rat(p.pitch), _rat(p.offset),
+                            p.tile_w, p.tile_h)
+    t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32).reshape(-1))
+    sz = np.ascontiguousarray(np.asarray(cluster_sizes, dtype=np.int32))
+    flags = (LFR_REMAP if remap else 0) | (LFR_CULL_UNREFERENCED if cull else 0)
+    opts = lfr_render_opts(int(sz[0]), flags, (c_float * 3)(0, 0, 0), 0, 0)
+    out = torch.empty((p.height, p.width, 3), dtype=torch.float32, device=scene.means.device)
+    ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
+    res = (lfr_tune_result * (len(t) // 2 * len(sz)))()
+    best = lfr_tune_result()
+    sc = scene.c_struct()
+    _check(library().lfr_autotune(ctx.handle, ctypes.byref(desc), ctypes.byref(sc), ca, len(ca), ctypes.byref(opts),
+                                  t.ctypes.data_as(c_void_p), len(t) // 2, sz.ctypes.data_as(c_void_p), len(sz),
+                                  reps, _ptr(out), res, ctypes.byref(best)), ctx.handle)
+    return best.as_dict(), [r.as_dict() for r in res]
 
 
 def project(ctx: Context, scene: DeviceScene, cam_packed, width, height):

@@ -49,6 +49,7 @@ DISPLAYS = [
     get_workload("outdoor").display,
     DisplayParams(250, 139, 7, Rational(-3, 11), Rational(17, 3), Rational(-5, 7), 8, 8),
     DisplayParams(250, 139, 11, Rational(1, 6), Rational(23, 5), Rational(1, 2), 32, 32),
+    DisplayParams(250, 139, 9, Rational(1, 5), Rational(31, 5), Rational(0), 64, 32),
     DisplayParams(77, 41, 9, Rational(2, 7), Rational(9, 2), Rational(0), 16, 8),
     DisplayParams(1, 1, 3, Rational(1, 6), Rational(5), Rational(0), 8, 8),
 ]
@@ -219,7 +220,7 @@ def test_depth_chunking_does_not_change_the_image(lib, tiny_setup, S, remap):
     d.close()
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8)])
+@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64)])
 def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     lfr, ctx = lib
     w, scene, cams, V, ds = tiny_setup
@@ -234,14 +235,30 @@ def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     dt.close()
 
 
+def test_autotune_reports_every_candidate(lib, tiny_setup):
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("autotune")
+    tiles = ((16, 16), (32, 32), (64, 32))
+    best, res = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(2, 8), tiles=tiles, reps=2)
+    assert len(res) == 6
+    assert [(r["tile_w"], r["tile_h"], r["cluster_size"]) for r in res] == [
+        (tw, th, S) for (tw, th) in tiles for S in (2, 8)]
+    assert all(r["ms"] > 0 and r["pairs"] > 0 for r in res)
+    assert best["ms"] == min(r["ms"] for r in res)
+    with pytest.raises(lfr.LfrError) as ei:
+        lfr.autotune(ctx, w.display, ds, cams, tiles=((12, 16),))
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+
+
 def test_fullframe_interlace_equals_exact_path(lib, tiny_setup):
     lfr, ctx = lib
     w, scene, cams, V, ds = tiny_setup
     say("full-frame + interlace vs exact path")
     d = _display(lfr, ctx, w.display)
     exact = _render(lfr, ctx, d, ds, cams, cluster_size=1)
-    for vb in (1, 5, 16):
-        ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=vb)
+    for vb, tile in ((1, 16), (5, 8), (16, 32)):
+        ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=vb, tile=tile)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ff.cpu().numpy(), exact)
     ff_all = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=7, cull=False)
