@@ -48,7 +48,35 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=96)
+    ap.add_argument("--tile", default=None, help="WxH tile shape; default: autotuned")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run three 256 MiB device copies (a known-size reference for HBM counters)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the sources the blend kernel is built from; counter summaries
+    in profiles/ apply only to the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("blend.hip", "lfr_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_04509_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, tile):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none for this workload, tile shape and kernel source."""
+    path = os.path.join(ROOT, "profiles", "blend_remap_outdoor_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if (t.get("kernel") != kernel or t.get("workload_name") != workload or t.get("tile") != list(tile)
+            or t.get("source_sha256") != kernel_source_hash()):
+        return None
+    return t["hbm_bytes_per_launch"]
 
 
 def timed(fn, steps, sync):
@@ -111,6 +139,13 @@ def main():
     from workloads import get_workload
     from workloads.cameras import pack_cameras
 
+    if args.copy_probe:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = get_workload(args.workload)
     log("generating", w.name)
     scene = w.make_scene()
@@ -122,9 +157,14 @@ def main():
     sync = torch.cuda.synchronize
     S = args.cluster_size
     # tile shape: the image does not depend on it, so pick the fastest (untimed)
-    best, tune = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(S,), reps=2)
-    log("autotune", best)
-    params = w.display.with_tile(best["tile_w"], best["tile_h"])
+    if args.tile:
+        tw, th = (int(v) for v in args.tile.lower().split("x"))
+        tune = None
+    else:
+        best, tune = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(S,), reps=2)
+        log("autotune", best)
+        tw, th = best["tile_w"], best["tile_h"]
+    params = w.display.with_tile(tw, th)
     disp = lfr.Display(ctx, params)
 
     def frame(cs=S, remap=True, timing=False):
@@ -143,6 +183,7 @@ def main():
     stages = {k: 0.0 for k in ("ms_project", "ms_depth_sort", "ms_keygen", "ms_sort", "ms_ranges", "ms_blend",
                                "ms_sort_scatter")}
     scatter_launches = 0
+    blend_launches = 0
     sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -151,6 +192,7 @@ def main():
         for k in stages:
             stages[k] += st[k]
         scatter_launches += st["sort_scatter_launches"]
+        blend_launches += st["blend_launches"]
     sync()
     sec = (time.perf_counter() - t0) / args.steps
     stages = {k: v / args.steps for k, v in stages.items()}
@@ -159,10 +201,17 @@ def main():
 
     # the dominant kernel: the blend (one launch per frame) or the scatter of
     # the tile sort (one launch per radix pass)
+    # blend: one launch per blended depth chunk; flops per launch = the
+    # frame's algorithmic flops over its launches
     flops = FLOPS_PER_EVAL * work["evals"] + FLOPS_PER_BLEND * work["blended"]
-    blend_alu = {"bound": "alu", "kernel": "blend_remap_kernel", "launch_ms": stages["ms_blend"],
-                 "achieved": flops / (stages["ms_blend"] * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
-                 "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"], "traffic": None}
+    bl = max(blend_launches / args.steps, 1.0)
+    blend_ms = stages["ms_blend"] / bl
+    blend_alu = {"bound": "alu", "kernel": "blend_remap_kernel<false>", "launch_ms": blend_ms,
+                 "launches_per_frame": bl, "flops_per_launch": flops / bl,
+                 "achieved": flops / bl / (blend_ms * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
+                 "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"],
+                 "traffic": measured_traffic("blend_remap_kernel<false>", w.name,
+                                               (params.tile_w, params.tile_h))}
     blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
     # tile sort: every chunk's pairs pass through ceil(tile_bits / 8) scatter
     # launches, each reading and writing (key, value) = 16 B per pair
@@ -190,7 +239,7 @@ def main():
                                 f"{w.display.tan_slant.den}, pitch {w.display.pitch.num}/{w.display.pitch.den}"),
                    "cluster_size": S, "remap": True, "tile": [params.tile_w, params.tile_h],
                    "parallelism": "single GPU"},
-        "autotune": tune,
+        "autotune": tune, "kernel_source_sha256": kernel_source_hash(),
         "stages_ms": stages, "pairs": work["pairs"], "chunks": work["chunks"], "clusters": work["clusters"],
         "views": work["views"],
         "roofline": roofline, "roofline_other": other, "fwd_bwd_ms": None,

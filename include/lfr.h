@@ -123,6 +123,7 @@ typedef struct {
     uint64_t blended;          /* of those, contributions blended               */
     float ms_sort_scatter;     /* LFR_TIMING: scatter launches of the tile sort */
     int32_t sort_scatter_launches;
+    int32_t blend_launches;    /* blend kernel launches (one per blended chunk) */
 } lfr_stats;
 
 /* One projected Gaussian (48 bytes), as returned by lfr_project:

@@ -896,9 +896,13 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
                 HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
             else
                 HIPCHK(ctx, launch_blend_rowmajor(bp, s));
-            if (!last)
+            const size_t e1 = tm.mark(s);
+            tm.span(kStBlend, e0, e1);
+            ++ctx->stats.blend_launches;
+            if (!last) {
                 HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
-            tm.span(kStBlend, e0, tm.mark(s));
+                tm.span(kStRanges, e1, tm.mark(s));
+            }
             blend_ran = true;
         }
         if (last) break;
@@ -907,7 +911,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     }
     tm.span(kStTotal, t0, tm.mark(s));
     ctx->stats.pairs = pairs;
-    ctx->stats.chunks = chunks;
+    ctx->stats.chunks = chunks;  // blend_launches was counted in the loop
     ctx->stats.clusters = vt.n_clusters;
     ctx->stats.views = vt.n_views;
     ctx->stats.tasks = remap ? ts->n : d->T;

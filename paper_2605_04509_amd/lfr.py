@@ -69,7 +69,7 @@ class lfr_stats(Structure):
                 ("ms_project", c_float), ("ms_depth_sort", c_float), ("ms_keygen", c_float),
                 ("ms_sort", c_float), ("ms_ranges", c_float), ("ms_blend", c_float),
                 ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64),
-                ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32)]
+                ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32), ("blend_launches", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
