@@ -15,6 +15,8 @@ Functions and the passages they follow:
 * :func:`render_view`     -- section 3.3 (standard full-frame blend)
 * :func:`render_interlaced_fullframe` -- render every view, then sample the
   subpixel each view owns (the full-frame-then-interlace definition)
+* :func:`grad_subpixels`  -- the same renderer in double precision and its
+  analytic derivative (chain rule through Eq. 9-10, 4.2, Eq. 4-6)
 """
 from __future__ import annotations
 
@@ -26,7 +28,8 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lfr_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("lfr_oracle.c", "lfr_oracle_grad.c")]
+_DEPS = _SRCS + [os.path.join(_HERE, f) for f in ("lfr_oracle.h", "lfr_oracle_impl.h")]
 _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "liboracle.so")
 _lock = threading.Lock()
@@ -43,10 +46,10 @@ assert PROJ_DTYPE.itemsize == 48
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no FMA contraction) into ``_build/``."""
     os.makedirs(_BUILD, exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _DEPS):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -73,6 +76,9 @@ def _load():
             lib.orc_render_subpixels.restype = ctypes.c_int
             lib.orc_render_view.argtypes = [i64, i32, P, P, P, P, P, P, i32, i32, P, P, P, P]
             lib.orc_render_view.restype = None
+            lib.orc_grad_subpixels.argtypes = [i64, i32, P, P, P, P, P, P, i32, P, i32, i32, i32, P,
+                                               i64, P, P, i32, P, P, P, P, P, P, P]
+            lib.orc_grad_subpixels.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -190,3 +196,39 @@ def render_interlaced_fullframe(scene, cams_packed, display, V, bg=(0.0, 0.0, 0.
         mask = V == j
         out[mask] = img[mask]
     return out
+
+
+GRAD_NAMES = ("means", "log_scales", "quats", "opacities", "sh")
+
+
+def grad_subpixels(scene, cams_packed, display, V, cluster_size, samples, gout=None,
+                   bg=(0.0, 0.0, 0.0), mode=1, grads=True):
+    """Double-precision values of the given subpixels and, with ``grads``,
+    the derivative of sum(gout * values) with respect to every scene
+    parameter.  Returns (values [n] f64, signatures [n] u64, grads dict or
+    None).  ``mode`` 1 takes the discrete decisions like
+    :func:`render_subpixels`, 0 on the double values."""
+    arrs, ptrs = _scene_args(scene)
+    cams = _f32(cams_packed).reshape(-1, 16)
+    V = np.ascontiguousarray(V, dtype=np.int32)
+    samples = np.ascontiguousarray(samples, dtype=np.int64)
+    n = samples.shape[0]
+    bgv = _f32(bg)
+    out = np.empty(n, dtype=np.float64)
+    sig = np.empty(n, dtype=np.uint64)
+    g = None
+    gp = [None] * 5
+    if grads:
+        gv = np.ascontiguousarray(gout if gout is not None else np.ones(n), dtype=np.float64)
+        if gv.shape != (n,):
+            raise ValueError("gout must have one entry per sample")
+        g = {k: np.empty(a.shape, dtype=np.float64) for k, a in zip(GRAD_NAMES, arrs)}
+        gp = [_ptr(g[k]) for k in GRAD_NAMES]
+    else:
+        gv = None
+    rc = _load().orc_grad_subpixels(scene.num_gaussians, scene.sh_degree, *ptrs, _ptr(cams), cams.shape[0],
+                                    _ptr(V), display.width, display.height, cluster_size, _ptr(bgv), n,
+                                    _ptr(samples), _ptr(gv), mode, _ptr(out), _ptr(sig), *gp)
+    if rc != 0:
+        raise ValueError("invalid gradient-oracle arguments")
+    return out, sig, g

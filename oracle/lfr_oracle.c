@@ -22,18 +22,12 @@
  * Parity pins live in tests/test_oracle_*.py.
  */
 #include "lfr_oracle.h"
+#include "lfr_oracle_impl.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define ALPHA_MIN (1.0f / 255.0f)   /* alpha cutoff, decided in float32     */
-#define T_STOP    1e-4f             /* transmittance stop, decided in float32 */
-#define ALPHA_MAX 0.99              /* alpha clamp                          */
-#define NEAR_Z    0.2f              /* near plane on the float32 depth      */
-#define DILATION  0.3               /* added to the 2D covariance diagonal  */
-#define CLAMP_FOV 1.3               /* Jacobian clamp, in units of tan(fov/2) */
-#define U32 5.9604644775390625e-08  /* float32 unit roundoff 2^-24 */
 #define FLAG_SAFETY 4.0
 
 /* ------------------------------------------------------------------------ */
@@ -186,13 +180,7 @@ void orc_sh_basis(int32_t degree, const double d[3], double *Y)
 /* Eq. 4-6: projection                                                      */
 /* ------------------------------------------------------------------------ */
 
-typedef struct {
-    double R[9], t[3], fx, fy, cx, cy;
-    double limx, limy;    /* Jacobian clamp on x/z and y/z */
-    double campos[3];     /* camera centre = -R^T t        */
-} cam_d;
-
-static void load_cam(const float *c, int32_t W, int32_t H, cam_d *o)
+void orc_load_cam(const float *c, int32_t W, int32_t H, orc_cam *o)
 {
     for (int k = 0; k < 9; ++k) o->R[k] = c[k];
     for (int k = 0; k < 3; ++k) o->t[k] = c[9 + k];
@@ -206,10 +194,10 @@ static void load_cam(const float *c, int32_t W, int32_t H, cam_d *o)
         o->campos[a] = -((o->R[0 + a] * o->t[0] + o->R[3 + a] * o->t[1]) + o->R[6 + a] * o->t[2]);
 }
 
-static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+double orc_clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 static void project_one(const float *mu, const float *ls, const float *q, float o,
-                        const float *sh, int32_t nb, int32_t deg, const cam_d *c,
+                        const float *sh, int32_t nb, int32_t deg, const orc_cam *c,
                         orc_proj *out)
 {
     memset(out, 0, sizeof *out);
@@ -264,8 +252,8 @@ static void project_one(const float *mu, const float *ls, const float *q, float 
             Vc[a * 3 + b] = (T1[a * 3 + 0] * R[b * 3 + 0] + T1[a * 3 + 1] * R[b * 3 + 1])
                           + T1[a * 3 + 2] * R[b * 3 + 2];
     /* EWA: Jacobian of the pinhole at the (clamped) mean direction */
-    double cxl = clampd(ux, -c->limx, c->limx);
-    double cyl = clampd(uy, -c->limy, c->limy);
+    double cxl = orc_clampd(ux, -c->limx, c->limx);
+    double cyl = orc_clampd(uy, -c->limy, c->limy);
     double j00 = c->fx / tz, j02 = -(c->fx * cxl) / tz;
     double j11 = c->fy / tz, j12 = -(c->fy * cyl) / tz;
     /* K = J Vc (rows 0 and 1), Sigma2D = K J^T */
@@ -310,8 +298,8 @@ void orc_project(int64_t M, int32_t deg, const float *means, const float *log_sc
                  const float *quats, const float *opac, const float *sh, const float *cam,
                  int32_t W, int32_t H, orc_proj *out)
 {
-    cam_d c;
-    load_cam(cam, W, H, &c);
+    orc_cam c;
+    orc_load_cam(cam, W, H, &c);
     int32_t nb = (deg + 1) * (deg + 1);
     for (int64_t i = 0; i < M; ++i)
         project_one(means + 3 * i, log_scales + 3 * i, quats + 4 * i, opac[i],

@@ -93,6 +93,28 @@ void orc_render_view(int64_t M, int32_t sh_degree, const float *means,
                      int32_t W, int32_t H, const float *bg, float *img,
                      int32_t *flags, double *tflag);
 
+/* Gradient oracle (lfr_oracle_grad.c).  The renderer of orc_render_subpixels
+ * evaluated in double precision with no float32 rounding of the projected
+ * attributes, and the analytic derivative of F = sum_s gout[s] * I[s] with
+ * respect to every scene parameter (chain rule through Eq. 9-10, the reuse
+ * rule of section 4.2, Eq. 4-6).  mode 0: the discrete decisions (validity,
+ * depth order, 1/255 cutoff, 1e-4 stop, 0.99 clamp) are taken on the double
+ * values; mode 1: as orc_render_subpixels takes them (float32 attributes).
+ *   out   (may be NULL) the double-precision value of every sample,
+ *   sig   (may be NULL) a 64-bit hash of every sample's decisions,
+ *   d_*   (NULL = values only) dF/d(parameter), [M,3] [M,3] [M,4] [M] [M,B,3],
+ *         overwritten.
+ * Returns 0, or -1 for invalid arguments. */
+int orc_grad_subpixels(int64_t M, int32_t sh_degree, const float *means,
+                       const float *log_scales, const float *quats,
+                       const float *opacities, const float *sh,
+                       const float *cams, int32_t N, const int32_t *V,
+                       int32_t W, int32_t H, int32_t S, const float *bg,
+                       int64_t n_samples, const int64_t *samples,
+                       const double *gout, int32_t mode, double *out,
+                       uint64_t *sig, double *d_means, double *d_log_scales,
+                       double *d_quats, double *d_opacities, double *d_sh);
+
 #ifdef __cplusplus
 }
 #endif
