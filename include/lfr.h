@@ -95,7 +95,7 @@ typedef struct {
 #define LFR_REMAP             1u  /* view-coherent thread order (section 4.3) */
 #define LFR_CULL_UNREFERENCED 2u  /* skip views/clusters no subpixel uses     */
 #define LFR_TIMING            4u  /* record per-stage times into lfr_stats    */
-#define LFR_SAVE_FOR_BACKWARD 8u  /* reserved for the differentiable path     */
+#define LFR_SAVE_FOR_BACKWARD 8u  /* keep what lfr_render_backward needs      */
 #define LFR_COUNT_WORK       16u  /* count blend evaluations (slower variant)  */
 typedef struct {
     int32_t cluster_size;   /* S >= 1; 1 = exact path, no reuse           */
@@ -124,6 +124,10 @@ typedef struct {
     float ms_sort_scatter;     /* LFR_TIMING: scatter launches of the tile sort */
     int32_t sort_scatter_launches;
     int32_t blend_launches;    /* blend kernel launches (one per blended chunk) */
+    /* lfr_render_backward (timed when the forward had LFR_TIMING) */
+    float ms_bwd_blend;        /* reverse blend into per-(Gaussian, cluster/view) grads */
+    float ms_bwd_project;      /* projection backward into per-Gaussian grads  */
+    float ms_bwd_total;
 } lfr_stats;
 
 /* One projected Gaussian (48 bytes), as returned by lfr_project:
@@ -209,6 +213,38 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
  * num_gaussians lfr_proj_record entries (caller-owned device memory). */
 lfr_status lfr_project(lfr_context *ctx, const lfr_scene *scene, const lfr_camera *host_cam,
                        int32_t width, int32_t height, lfr_proj_record *out_device);
+
+/* ---- differentiation ---------------------------------------------------- */
+
+/* Gradients with respect to the scene parameters: float32 device arrays with
+ * the shapes of the lfr_scene arrays (means [M,3], log_scales [M,3], quats
+ * [M,4], opacities [M], sh [M,(d+1)^2,3]).  Caller-owned; every element is
+ * overwritten. */
+typedef struct {
+    float *means, *log_scales, *quats, *opacities, *sh;
+} lfr_scene_grads;
+
+/* Backward of the last lfr_render on this context, which must have been
+ * called with LFR_SAVE_FOR_BACKWARD (and no other call that renders,
+ * projects, sorts, tunes or trims on this context in between; otherwise
+ * LFR_ERR_INVALID_ARG).  The paper defines the forward only; the backward
+ * is its exact derivative with the forward's discrete decisions held fixed
+ * (which Gaussians pass the 1/255 cutoff, where the 1e-4 transmittance stop
+ * falls, the 0.99 alpha clamp, the colour clamp at 0 and the Jacobian
+ * clamp; derivatives through an active clamp are 0), under the same reuse
+ * rule (section 4.2 Eq. 5-6: the 2D mean per view, covariance and colour per
+ * cluster).
+ *
+ * grad_out_device: float32 [H][W][3], dL/dI for the rendered image.
+ * display and scene: the ones the forward used (same values, same M and SH
+ * degree).  grads: written with dL/d(parameter); the quaternion gradient is
+ * with respect to the unnormalized input.  Per-(Gaussian, cluster) and
+ * per-(Gaussian, view) sums use float32 atomics, so results vary in the
+ * last bits between runs.  With LFR_SAVE_FOR_BACKWARD the forward bins all
+ * Gaussians in one depth chunk (same image) and keeps 8 bytes per subpixel
+ * (final transmittance, end of its blended list) plus its sorted lists. */
+lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
+                               const float *grad_out_device, const lfr_scene_grads *grads);
 
 /* ---- autotuning ------------------------------------------------------------- */
 

@@ -23,7 +23,7 @@ namespace {
 enum Slot {
     kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
-    kWork, kAlive, kAliveBits, kState, kTaskAlive, kNumSlots
+    kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kNumSlots
 };
 
 struct Buf {
@@ -32,6 +32,29 @@ struct Buf {
 };
 
 }  // namespace
+
+// What lfr_render_backward needs from the last LFR_SAVE_FOR_BACKWARD render:
+// pointers into the context workspace and the display's work items, valid
+// until the next call that uses the workspace.
+struct SavedForward {
+    bool valid = false;
+    const void *display = nullptr;
+    int64_t M = 0;
+    int deg = 0;
+    bool timing = false;
+    float bg[3] = {0.f, 0.f, 0.f};
+    int n_clusters = 0, n_views = 0, cbits = 0;
+    const DevCamera *cams = nullptr;
+    const int32_t *cluster_cam = nullptr, *view_cam = nullptr, *view_slot = nullptr;
+    const GaussRec *rec = nullptr;
+    const float2 *mean2d = nullptr;
+    const uint2 *ranges = nullptr;
+    const uint32_t *vals = nullptr;
+    const Task *tasks = nullptr;
+    int n_tasks = 0;
+    const float *save_T = nullptr;
+    const uint32_t *save_end = nullptr;
+};
 
 struct lfr_context {
     int device = 0;
@@ -43,6 +66,7 @@ struct lfr_context {
     void *pinned = nullptr;
     size_t pinned_n = 0;
     Timer timer;
+    SavedForward saved;
 };
 
 struct lfr_display {
@@ -478,10 +502,13 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
     return LFR_OK;
 }
 
-lfr_status begin(lfr_context *ctx)
+// Every entry point starts here.  Calls that use the workspace drop the
+// saved forward (keep_saved = false).
+lfr_status begin(lfr_context *ctx, bool keep_saved = false)
 {
     if (!ctx) return LFR_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (!keep_saved) ctx->saved.valid = false;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     return LFR_OK;
 }
@@ -527,6 +554,19 @@ lfr_status finish_timing(lfr_context *ctx)
     int n = 0;
     for (const auto &sp : tm.spans) n += sp.stage == kStScatter;
     st.sort_scatter_launches = n;
+    return LFR_OK;
+}
+
+lfr_status finish_backward_timing(lfr_context *ctx)
+{
+    const Timer &tm = ctx->timer;
+    if (!tm.on || tm.used == 0) return LFR_OK;
+    HIPCHK(ctx, hipEventSynchronize(tm.pool[tm.used - 1]));
+    float ms[kNumStages];
+    tm.sum(ms);
+    ctx->stats.ms_bwd_blend = ms[kStBwdBlend];
+    ctx->stats.ms_bwd_project = ms[kStBwdProject];
+    ctx->stats.ms_bwd_total = ms[kStBwdTotal];
     return LFR_OK;
 }
 
@@ -647,7 +687,7 @@ static lfr_display *new_display(lfr_context *ctx, int W, int H, int N, int tw, i
 
 lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lfr_display **out)
 {
-    CHK(begin(ctx));
+    CHK(begin(ctx, true));
     if (!desc || !out) return fail(ctx, LFR_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     const lfr_display_desc &D = *desc;
@@ -701,7 +741,7 @@ lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lf
 lfr_status lfr_display_create_from_map(lfr_context *ctx, int32_t W, int32_t H, int32_t N, const int32_t *view_map,
                                        int32_t tw, int32_t th, lfr_display **out)
 {
-    CHK(begin(ctx));
+    CHK(begin(ctx, true));
     if (!view_map || !out) return fail(ctx, LFR_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || N < 1 || N > 65535)
@@ -811,6 +851,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
     const bool remap = (opts->flags & LFR_REMAP) != 0;
     const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
+    const bool save = (opts->flags & LFR_SAVE_FOR_BACKWARD) != 0;
     const int S = opts->cluster_size;
     const int64_t M = scene->num_gaussians;
     const int64_t nsub = 3ll * d->W * d->H;
@@ -869,12 +910,21 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
         CHK(ws_get_t(ctx, kWork, 2, &bp.work));
         HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, s));
     }
+    bp.save_T = nullptr;
+    bp.save_end = nullptr;
+    if (save) {
+        CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
+        CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
+    }
     const BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.cbits, alive_bits, pr.items);
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
-    int64_t r0 = 0, len = opts->first_chunk > 0
+    // (one chunk holding every rank when the lists are kept for the backward)
+    int64_t r0 = 0, len = save ? std::max<int64_t>(M, 1)
+                          : opts->first_chunk > 0
                               ? (int64_t)opts->first_chunk
                               : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    Chunk saved_chunk;
     bool blend_ran = false;
     uint64_t pairs = 0;
     int chunks = 0;
@@ -883,6 +933,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
         const bool last = r0 + len >= M;
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch));
+        saved_chunk = ch;
         if (blend_ran && ch.alive == 0) break;  // every subpixel saturated: all outputs written
         ++chunks;
         pairs += ch.P;
@@ -910,6 +961,30 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
         len *= 4;
     }
     tm.span(kStTotal, t0, tm.mark(s));
+    if (save) {
+        SavedForward &sv = ctx->saved;
+        sv.display = d;
+        sv.M = M;
+        sv.deg = scene->sh_degree;
+        sv.timing = (opts->flags & LFR_TIMING) != 0;
+        for (int k = 0; k < 3; ++k) sv.bg[k] = opts->background[k];
+        sv.n_clusters = vt.n_clusters;
+        sv.n_views = vt.n_views;
+        sv.cbits = pr.cbits;
+        sv.cams = dt.cams;
+        sv.cluster_cam = dt.cluster_cam;
+        sv.view_cam = dt.view_cam;
+        sv.view_slot = dt.view_slot;
+        sv.rec = pr.rec;
+        sv.mean2d = pr.mean2d;
+        sv.ranges = saved_chunk.ranges;
+        sv.vals = saved_chunk.vals;
+        sv.tasks = ts->d_tasks;
+        sv.n_tasks = ts->n;
+        sv.save_T = bp.save_T;
+        sv.save_end = bp.save_end;
+        sv.valid = true;
+    }
     ctx->stats.pairs = pairs;
     ctx->stats.chunks = chunks;  // blend_launches was counted in the loop
     ctx->stats.clusters = vt.n_clusters;
@@ -926,6 +1001,67 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
     return finish_timing(ctx);
 }
 
+lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
+                               const float *grad_out_device, const lfr_scene_grads *grads)
+{
+    CHK(begin(ctx, true));
+    const SavedForward &sv = ctx->saved;
+    if (!sv.valid)
+        return fail(ctx, LFR_ERR_INVALID_ARG,
+                    "no saved forward: call lfr_render with LFR_SAVE_FOR_BACKWARD first (and nothing that uses "
+                    "this context's workspace in between)");
+    if (!display || (const void *)display != sv.display)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "display differs from the saved forward's");
+    CHK(check_scene(ctx, scene));
+    if (scene->num_gaussians != sv.M || scene->sh_degree != sv.deg)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "scene (M %lld, degree %d) differs from the saved forward's (M %lld, "
+                    "degree %d)", (long long)scene->num_gaussians, scene->sh_degree, (long long)sv.M, sv.deg);
+    if (!grad_out_device) return fail(ctx, LFR_ERR_INVALID_ARG, "grad_out is NULL");
+    if (!grads) return fail(ctx, LFR_ERR_INVALID_ARG, "grads is NULL");
+    const int64_t M = sv.M;
+    if (M > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacities || !grads->sh))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "a gradient array pointer is NULL");
+    hipStream_t s = ctx->stream;
+    GradRec *d_rec;
+    float2 *d_mean;
+    CHK(ws_get_t(ctx, kDRec, (size_t)std::max<int64_t>(M * sv.n_clusters, 1), &d_rec));
+    CHK(ws_get_t(ctx, kDMean, (size_t)std::max<int64_t>(M * sv.n_views, 1), &d_mean));
+    Timer &tm = ctx->timer;
+    tm.reset(sv.timing);
+    const size_t t0 = tm.mark(s);
+    HIPCHK(ctx, launch_fill_u32((uint32_t *)d_rec, 0u, M * sv.n_clusters * 8, s));
+    HIPCHK(ctx, launch_fill_u32((uint32_t *)d_mean, 0u, M * sv.n_views * 2, s));
+    BwdParams bp;
+    bp.W = display->W;
+    bp.M = M;
+    bp.cluster_bits = sv.cbits;
+    bp.V = display->d_V;
+    bp.psi = display->d_psi;
+    bp.view_slot = sv.view_slot;
+    bp.ranges = sv.ranges;
+    bp.vals = sv.vals;
+    bp.rec = sv.rec;
+    bp.mean2d = sv.mean2d;
+    for (int k = 0; k < 3; ++k) bp.bg[k] = sv.bg[k];
+    bp.grad_out = grad_out_device;
+    bp.save_T = sv.save_T;
+    bp.save_end = sv.save_end;
+    bp.d_rec = d_rec;
+    bp.d_mean2d = d_mean;
+    const size_t e0 = tm.mark(s);
+    if (M > 0 && sv.ranges) HIPCHK(ctx, launch_blend_backward(bp, sv.tasks, sv.n_tasks, s));
+    const size_t e1 = tm.mark(s);
+    tm.span(kStBwdBlend, e0, e1);
+    SceneGrads sg{grads->means, grads->log_scales, grads->quats, grads->opacities, grads->sh};
+    HIPCHK(ctx, launch_project_backward(scene_dev(scene), sv.cams, sv.n_clusters, sv.cluster_cam, sv.n_views,
+                                        sv.view_cam, d_rec, d_mean, sg, s));
+    const size_t e2 = tm.mark(s);
+    tm.span(kStBwdProject, e1, e2);
+    tm.span(kStBwdTotal, t0, e2);
+    ctx->stats.ms_bwd_blend = ctx->stats.ms_bwd_project = ctx->stats.ms_bwd_total = 0.0f;
+    return finish_backward_timing(ctx);
+}
+
 lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
                                           const lfr_camera *host_cams, int32_t num_cams,
                                           const lfr_render_opts *opts, int32_t view_batch, float *out_device)
@@ -933,6 +1069,8 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
     CHK(begin(ctx));
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
     if (view_batch < 1) return fail(ctx, LFR_ERR_INVALID_ARG, "view_batch must be >= 1");
+    if (opts->flags & LFR_SAVE_FOR_BACKWARD)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "LFR_SAVE_FOR_BACKWARD applies to lfr_render only");
     const int ft = opts->fullframe_tile ? opts->fullframe_tile : 16;
     if (ft != 8 && ft != 16 && ft != 32)
         return fail(ctx, LFR_ERR_INVALID_ARG, "fullframe_tile must be 8, 16 or 32");

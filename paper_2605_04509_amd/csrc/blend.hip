@@ -20,13 +20,27 @@ namespace lfr {
 // +inf and alpha 0, so the Gaussian is skipped without a branch.
 constexpr float kFarMean = 1e30f;
 
-__device__ __forceinline__ float step_alpha(const float4 a, const float2 m, float px, float py)
+// Intermediates of one step, shared by the forward and the reverse blend so
+// that both evaluate alpha with the same float32 operations.
+struct StepEval {
+    float dy, w, ex, raw;  // raw = o 2^-E before the clamp
+};
+
+__device__ __forceinline__ float step_eval(const float4 a, const float2 m, float px, float py, StepEval &s)
 {
     const float dx = px - m.x;
-    const float dy = py - m.y;
-    const float w = fmaf(a.y, dy, dx);
-    const float E = fmaf(a.x * w, w, (a.z * dy) * dy);
-    return fminf(kAlphaMax, a.w * __builtin_amdgcn_exp2f(-E));
+    s.dy = py - m.y;
+    s.w = fmaf(a.y, s.dy, dx);
+    const float E = fmaf(a.x * s.w, s.w, (a.z * s.dy) * s.dy);
+    s.ex = __builtin_amdgcn_exp2f(-E);
+    s.raw = a.w * s.ex;
+    return fminf(kAlphaMax, s.raw);
+}
+
+__device__ __forceinline__ float step_alpha(const float4 a, const float2 m, float px, float py)
+{
+    StepEval s;
+    return step_eval(a, m, px, py, s);
 }
 
 __device__ __forceinline__ float2 sanitize_mean(float2 m)
@@ -65,7 +79,9 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 // and the wavefront leaves as soon as all of its lanes have stopped (checked
 // every 16 Gaussians).  Batches are padded to a multiple of 4 with
 // zero-opacity entries, whose alpha is 0 and never passes the cutoff.
-template <bool kCount>
+// kSave (single-chunk renders) also writes each subpixel's final T and the
+// end of its blended list for the backward.
+template <bool kCount, bool kSave>
 __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
                                                           int n_tasks, int per)
 {
@@ -105,6 +121,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     if (!bp.first && active) load_state(bp, at, T, C, done);
     const bool was_done = done;
     unsigned long long n_eval = 0, n_blend = 0;
+    uint32_t endp = 0;
     __syncthreads();
     int slots[kMaxWaveViews];
 #pragma unroll
@@ -155,6 +172,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
                     }
                     C = take ? fmaf(s_c[g * 4 + u] * alpha, T, C) : C;
                     T = take ? Tn : T;
+                    if (kSave) endp = take ? base + (uint32_t)g + 1u : endp;
                     done = done || (pass && !take);
                 }
                 if (__ballot(!done) == 0) break;
@@ -166,7 +184,13 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     const uint64_t newly = __ballot(active && done && !was_done);
     const bool all_done = __ballot(!done) == 0;
     if (all_done || bp.last) {
-        if (active) bp.out[p] = C + T * bp.bg[u];
+        if (active) {
+            bp.out[p] = C + T * bp.bg[u];
+            if (kSave) {
+                bp.save_T[p] = T;
+                bp.save_end[p] = endp;
+            }
+        }
     } else if (active) {
         bp.state[at] = make_float2(done ? -T : T, C);
     }
@@ -188,7 +212,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
 // thread takes subpixels r = tid, tid+256, ... of the tile's row-major list
 // and walks its own (tile, cluster) list from global memory.  State is kept
 // per panel subpixel.
-template <bool kCount>
+template <bool kCount, bool kSave>
 __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
 {
     unsigned long long n_eval = 0, n_blend = 0;
@@ -218,6 +242,7 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
         const GaussRec *rec = bp.rec + (int64_t)c * bp.M;
         const float2 *mu = bp.mean2d + (int64_t)slot * bp.M;
         const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+        uint32_t endp = 0;
         for (uint32_t e = range.x; e < range.y; ++e) {
             const uint32_t i = bp.vals[e];
             const GaussRec g = rec[i];
@@ -232,9 +257,14 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
             const float col = u == 0 ? g.c.x : (u == 1 ? g.c.y : g.c.z);
             C = fmaf(col * alpha, T, C);
             T = Tn;
+            endp = e + 1;
             if (kCount) ++n_blend;
         }
         if (done || bp.last) bp.out[p] = C + T * bp.bg[u];
+        if (kSave) {
+            bp.save_T[p] = T;
+            bp.save_end[p] = endp;
+        }
         if (done) {
             if (!bp.last) bp.state[p] = make_float2(-T, C);
             atomicSub(&bp.tc_alive[list], 1u);
@@ -318,24 +348,192 @@ __global__ void __launch_bounds__(256) interlace_kernel(const uint16_t *__restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse blend (derivative of Eq. 9-10 with the forward's decisions held).
+//
+// For one subpixel with blended list e = 0..n-1 (alpha_e, colour c_e, T_e the
+// transmittance in front of e) and output I = sum_e c_e alpha_e T_e + T_n bg:
+//   dI/dc_e     = alpha_e T_e
+//   dI/dalpha_e = c_e T_e - (sum_{h>e} c_h alpha_h T_h + T_n bg) / (1 - alpha_e)
+// Walking the list back to front from its saved end, T_e = T_{e+1}/(1-alpha_e)
+// recovers the transmittance from the saved T_n, and the bracket is a running
+// sum.  Through alpha = o 2^-E (no clamp active): dalpha/do = 2^-E,
+// dalpha/dE = -alpha ln 2, and E = A'(dx + beta dy)^2 + G' dy^2 with
+// (dx, dy) = sample - mean gives the record and mean derivatives.
+//
+// One wavefront per work item, as in the forward: the (tile, cluster) list is
+// staged 64 entries at a time from the top of the wavefront's highest list
+// end downwards.  Each entry's seven record derivatives (and the two mean
+// derivatives per view of the wavefront) are summed over the 64 lanes and
+// added to the per-(cluster, Gaussian) and per-(view, Gaussian) gradient
+// buffers with one float atomic per value.
+// ---------------------------------------------------------------------------
+constexpr float kLn2 = 0.69314718055994530942f;
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_get(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
+}
+
+// Sum over the 64 lanes, returned in every lane: DPP butterflies inside each
+// 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror), then the four row sums through two lane swaps.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += dpp_get<0xB1>(v);
+    v += dpp_get<0x4E>(v);
+    v += dpp_get<0x141>(v);
+    v += dpp_get<0x140>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const Task *__restrict__ tasks,
+                                                             int n_tasks, int per)
+{
+    __shared__ float4 s_a[kWave];
+    __shared__ float s_c[kWave * 4];
+    __shared__ float2 s_mu[kMaxWaveViews][kWave];
+    __shared__ uint32_t s_i[kWave];
+    __shared__ int s_slot[kMaxWaveViews];
+
+    const int ti = xcd_task(blockIdx.x, per);
+    if (ti >= n_tasks) return;
+    const Task tk = tasks[ti];
+    const int lane = threadIdx.x;
+    const bool active = lane < (int)tk.count;
+    const uint32_t at = tk.start + (active ? lane : (int)tk.count - 1);
+    const uint32_t p = bp.psi[at];
+    const int j = bp.V[p];
+    const uint32_t pix = p / 3;
+    const int u = (int)(p - 3 * pix);
+    const uint32_t y = pix / (uint32_t)bp.W;
+    const uint32_t x = pix - y * (uint32_t)bp.W;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+
+    const int jprev = __shfl_up(j, 1, 64);
+    const bool first = lane == 0 || j != jprev;
+    const uint64_t runs = __ballot(first);
+    const int my_run = __popcll(runs & ((2ull << lane) - 1ull)) - 1;
+    const int n_runs = __popcll(runs);
+    if (first) s_slot[my_run] = bp.view_slot[j];
+
+    const float gout = active ? bp.grad_out[p] : 0.0f;
+    const uint32_t end = (active && gout != 0.0f) ? bp.save_end[p] : 0u;
+    float T = active ? bp.save_T[p] : 0.0f;
+    float rest = T * bp.bg[u];
+    const uint32_t list = (tk.tile << bp.cluster_bits) | tk.cluster;
+    const uint2 range = bp.ranges[list];
+    uint32_t hi = end;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+    __syncthreads();
+    if (hi <= range.x) return;
+    int slots[kMaxWaveViews];
+#pragma unroll
+    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = q < n_runs ? s_slot[q] : 0;
+    const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
+    float *drec = reinterpret_cast<float *>(bp.d_rec + (int64_t)tk.cluster * bp.M);
+    float *dmean = reinterpret_cast<float *>(bp.d_mean2d);
+
+    for (uint32_t top = hi; top > range.x;) {
+        const uint32_t b0 = top - range.x > (uint32_t)kWave ? top - (uint32_t)kWave : range.x;
+        const int nb = (int)(top - b0);
+        if (lane < nb) {
+            const uint32_t i = bp.vals[b0 + lane];
+            const GaussRec g = rec[i];
+            s_a[lane] = g.a;
+            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
+            s_i[lane] = i;
+#pragma unroll
+            for (int q = 0; q < kMaxWaveViews; ++q)
+                if (q < n_runs) s_mu[q][lane] = sanitize_mean(bp.mean2d[(int64_t)slots[q] * bp.M + i]);
+        }
+        __syncthreads();
+        for (int g = nb - 1; g >= 0; --g) {
+            const float4 a = s_a[g];
+            StepEval st;
+            const float alpha = step_eval(a, s_mu[my_run][g], px, py, st);
+            const bool on = b0 + (uint32_t)g < end && alpha >= kAlphaMin;
+            if (__ballot(on) == 0) continue;
+            const float c = s_c[g * 4 + u];
+            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+            const float Tg = T * inv;
+            const float dc = on ? gout * alpha * Tg : 0.0f;
+            const float da = gout * (c * Tg - rest * inv);
+            rest = on ? fmaf(c * alpha, Tg, rest) : rest;
+            T = on ? Tg : T;
+            // lanes that do not take this entry contribute exact zeros (their
+            // w may be huge for a view where the mean is invalid, so the
+            // products are selected, not multiplied by zero)
+            const bool smooth = on && st.raw <= kAlphaMax;
+            const float dE = -da * st.raw * kLn2;
+            const float t2 = 2.0f * a.x * st.w;
+            const float v0 = wave_sum(smooth ? dE * st.w * st.w : 0.0f);    // dA'
+            const float v1 = wave_sum(smooth ? dE * t2 * st.dy : 0.0f);     // dbeta
+            const float v2 = wave_sum(smooth ? dE * st.dy * st.dy : 0.0f);  // dG'
+            const float v3 = wave_sum(smooth ? da * st.ex : 0.0f);          // do
+            const float v4 = wave_sum(u == 0 ? dc : 0.0f);                  // dr
+            const float v5 = wave_sum(u == 1 ? dc : 0.0f);                  // dg
+            const float v6 = wave_sum(u == 2 ? dc : 0.0f);                  // db
+            const uint32_t i = s_i[g];
+            const float vr = lane == 0 ? v0 : lane == 1 ? v1 : lane == 2 ? v2 : lane == 3 ? v3
+                           : lane == 4 ? v4 : lane == 5 ? v5 : v6;
+            if (lane < 7) unsafeAtomicAdd(drec + (int64_t)i * 8 + lane, vr);
+            // the mean of the lane's view: d/dmean = -d/d(dx, dy)
+            const float dmx = smooth ? -dE * t2 : 0.0f;
+            const float dmy = smooth ? -dE * fmaf(t2, a.y, 2.0f * a.z * st.dy) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < kMaxWaveViews; ++q) {
+                if (q >= n_runs) break;
+                const float sx = wave_sum(my_run == q ? dmx : 0.0f);
+                const float sy = wave_sum(my_run == q ? dmy : 0.0f);
+                if (lane < 2 && (sx != 0.0f || sy != 0.0f))
+                    unsafeAtomicAdd(dmean + ((int64_t)slots[q] * bp.M + i) * 2 + lane, lane == 0 ? sx : sy);
+            }
+        }
+        __syncthreads();
+        top = b0;
+    }
+}
+
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
 {
     if (n_tasks == 0) return hipSuccess;
     const int per = (n_tasks + 7) / 8;
-    if (bp.work)
-        hipLaunchKernelGGL(blend_remap_kernel<true>, dim3((unsigned)(8 * per)), dim3(kWave), 0, s, bp, tasks, n_tasks, per);
+    const dim3 grid((unsigned)(8 * per)), block(kWave);
+    if (bp.work && bp.save_T)
+        hipLaunchKernelGGL((blend_remap_kernel<true, true>), grid, block, 0, s, bp, tasks, n_tasks, per);
+    else if (bp.work)
+        hipLaunchKernelGGL((blend_remap_kernel<true, false>), grid, block, 0, s, bp, tasks, n_tasks, per);
+    else if (bp.save_T)
+        hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks, per);
     else
-        hipLaunchKernelGGL(blend_remap_kernel<false>, dim3((unsigned)(8 * per)), dim3(kWave), 0, s, bp, tasks, n_tasks, per);
+        hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks, per);
     return hipGetLastError();
 }
 
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s)
 {
-    const int T = bp.TX * ((bp.H + bp.th - 1) / bp.th);
-    if (bp.work)
-        hipLaunchKernelGGL(blend_rowmajor_kernel<true>, dim3((unsigned)T), dim3(256), 0, s, bp);
+    const dim3 grid((unsigned)(bp.TX * ((bp.H + bp.th - 1) / bp.th))), block(256);
+    if (bp.work && bp.save_T)
+        hipLaunchKernelGGL((blend_rowmajor_kernel<true, true>), grid, block, 0, s, bp);
+    else if (bp.work)
+        hipLaunchKernelGGL((blend_rowmajor_kernel<true, false>), grid, block, 0, s, bp);
+    else if (bp.save_T)
+        hipLaunchKernelGGL((blend_rowmajor_kernel<false, true>), grid, block, 0, s, bp);
     else
-        hipLaunchKernelGGL(blend_rowmajor_kernel<false>, dim3((unsigned)T), dim3(256), 0, s, bp);
+        hipLaunchKernelGGL((blend_rowmajor_kernel<false, false>), grid, block, 0, s, bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
+{
+    if (n_tasks == 0) return hipSuccess;
+    const int per = (n_tasks + 7) / 8;
+    hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)(8 * per)), dim3(kWave), 0, s, bp, tasks, n_tasks, per);
     return hipGetLastError();
 }
 

@@ -43,6 +43,13 @@ struct GaussRec {
     float4 c;
 };
 
+// Per-(cluster, Gaussian) gradient record of the reverse blend, the same
+// layout as GaussRec: a = d(A', beta, G', opacity), c = d(r, g, b), unused.
+struct GradRec {
+    float4 a;
+    float4 c;
+};
+
 // A blend work item: up to 64 subpixels of one tile that all belong to one
 // cluster and to at most kMaxWaveViews distinct views, contiguous in Psi.
 struct Task {
@@ -77,7 +84,10 @@ struct TaskSet {
 
 // Stage timer: HIP events recorded on the working stream, summed per stage
 // after the frame.
-enum Stage { kStProject, kStDepthSort, kStKeygen, kStSort, kStRanges, kStBlend, kStScatter, kStTotal, kNumStages };
+enum Stage {
+    kStProject, kStDepthSort, kStKeygen, kStSort, kStRanges, kStBlend, kStScatter, kStTotal,
+    kStBwdBlend, kStBwdProject, kStBwdTotal, kNumStages
+};
 struct Timer {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -245,10 +255,44 @@ struct BlendParams {
     uint32_t *tc_alive;           // per (tile, cluster) list: unsaturated subpixels
     uint32_t *alive_total;        // unsaturated subpixels of the frame
     int first, last;              // first / last chunk of the frame
+    // kept for the backward (single-chunk renders only; null otherwise):
+    float *save_T;                // per subpixel: final transmittance
+    uint32_t *save_end;           // per subpixel: 1 + position of its last blended pair (0: none)
 };
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
                               hipStream_t s);
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
+
+// Reverse blend over the remapped work items of a saved single-chunk render.
+struct BwdParams {
+    int W;
+    int64_t M;
+    int cluster_bits;
+    const uint16_t *V;
+    const uint32_t *psi;
+    const int32_t *view_slot;     // [N] compact mean slot of view j
+    const uint2 *ranges;
+    const uint32_t *vals;
+    const GaussRec *rec;          // [K'][M]
+    const float2 *mean2d;         // [N'][M]
+    float bg[3];
+    const float *grad_out;        // [H][W][3] dL/dI
+    const float *save_T;
+    const uint32_t *save_end;
+    GradRec *d_rec;               // [K'][M], zeroed by the caller
+    float2 *d_mean2d;             // [N'][M], zeroed by the caller
+};
+hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, hipStream_t s);
+
+// Projection backward: per Gaussian, the record gradients of every cluster
+// and the mean gradients of every view -> parameter gradients.
+struct SceneGrads {
+    float *means, *log_scales, *quats, *opac, *sh;
+};
+hipError_t launch_project_backward(const SceneDev &sc, const DevCamera *cams, int n_clusters,
+                                   const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
+                                   const GradRec *d_rec, const float2 *d_mean2d, const SceneGrads &out,
+                                   hipStream_t s);
 
 struct FullFrameParams {
     int W, H, tw, th, TX, TY;

@@ -382,4 +382,301 @@ hipError_t launch_project_records(const SceneDev &sc, const DevCamera *cam, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Projection backward: the reverse of project_mean, project_full, cov3d and
+// sh_colour for the gradients the reverse blend left in the per-(cluster,
+// Gaussian) records and per-(view, Gaussian) means.  Double precision, one
+// thread per Gaussian, so every parameter gradient is written once without
+// atomics.  Clamped quantities (Jacobian direction, colour at 0) pass no
+// derivative.
+// ---------------------------------------------------------------------------
+
+// Real SH basis at (x, y, z) and its gradient, treating each basis function
+// as the polynomial it is written as (the direction's normalization is
+// chained separately).
+template <int DEG>
+__device__ inline void sh_basis_grad(double x, double y, double z, double Y[16], double Gx[16], double Gy[16],
+                                     double Gz[16])
+{
+    constexpr double pi = 3.14159265358979323846;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) Y[b] = Gx[b] = Gy[b] = Gz[b] = 0.0;
+    Y[0] = 0.5 * __builtin_sqrt(1.0 / pi);
+    if (DEG >= 1) {
+        const double c1 = __builtin_sqrt(3.0 / (4.0 * pi));
+        Y[1] = -c1 * y;  Gy[1] = -c1;
+        Y[2] = c1 * z;   Gz[2] = c1;
+        Y[3] = -c1 * x;  Gx[3] = -c1;
+    }
+    if (DEG >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        const double c2a = 0.5 * __builtin_sqrt(15.0 / pi);
+        const double c2b = 0.25 * __builtin_sqrt(5.0 / pi);
+        const double c2c = 0.25 * __builtin_sqrt(15.0 / pi);
+        Y[4] = c2a * (x * y);                  Gx[4] = c2a * y;          Gy[4] = c2a * x;
+        Y[5] = -c2a * (y * z);                 Gy[5] = -c2a * z;         Gz[5] = -c2a * y;
+        Y[6] = c2b * (2.0 * zz - xx - yy);     Gx[6] = -2.0 * c2b * x;   Gy[6] = -2.0 * c2b * y;  Gz[6] = 4.0 * c2b * z;
+        Y[7] = -c2a * (x * z);                 Gx[7] = -c2a * z;         Gz[7] = -c2a * x;
+        Y[8] = c2c * (xx - yy);                Gx[8] = 2.0 * c2c * x;    Gy[8] = -2.0 * c2c * y;
+        if (DEG >= 3) {
+            const double c3a = 0.25 * __builtin_sqrt(35.0 / (2.0 * pi));
+            const double c3b = 0.5 * __builtin_sqrt(105.0 / pi);
+            const double c3c = 0.25 * __builtin_sqrt(21.0 / (2.0 * pi));
+            const double c3d = 0.25 * __builtin_sqrt(7.0 / pi);
+            const double c3e = 0.25 * __builtin_sqrt(105.0 / pi);
+            Y[9] = -c3a * (y * (3.0 * xx - yy));
+            Gx[9] = -6.0 * c3a * x * y;            Gy[9] = -3.0 * c3a * (xx - yy);
+            Y[10] = c3b * (x * y * z);
+            Gx[10] = c3b * y * z;                  Gy[10] = c3b * x * z;        Gz[10] = c3b * x * y;
+            Y[11] = -c3c * (y * (4.0 * zz - xx - yy));
+            Gx[11] = 2.0 * c3c * x * y;            Gy[11] = -c3c * (4.0 * zz - xx - 3.0 * yy);
+            Gz[11] = -8.0 * c3c * y * z;
+            Y[12] = c3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+            Gx[12] = -6.0 * c3d * x * z;           Gy[12] = -6.0 * c3d * y * z;
+            Gz[12] = c3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+            Y[13] = -c3c * (x * (4.0 * zz - xx - yy));
+            Gx[13] = -c3c * (4.0 * zz - 3.0 * xx - yy);
+            Gy[13] = 2.0 * c3c * x * y;            Gz[13] = -8.0 * c3c * x * z;
+            Y[14] = c3e * (z * (xx - yy));
+            Gx[14] = 2.0 * c3e * x * z;            Gy[14] = -2.0 * c3e * y * z;  Gz[14] = c3e * (xx - yy);
+            Y[15] = -c3a * (x * (xx - 3.0 * yy));
+            Gx[15] = -3.0 * c3a * (xx - yy);       Gy[15] = 6.0 * c3a * x * y;
+        }
+    }
+}
+
+// d(loss)/d(pixel mean) in one camera -> d(loss)/d(world mean).
+__device__ inline void mean_grad(const DevCamera &c, const MeanProj &m, float2 dm, double dmu[3])
+{
+    const double dux = c.fx * (double)dm.x, duy = c.fy * (double)dm.y;
+    const double dtx = dux / m.tz, dty = duy / m.tz, dtz = -(dux * m.tx + duy * m.ty) / (m.tz * m.tz);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dmu[k] += (c.R[k] * dtx + c.R[3 + k] * dty) + c.R[6 + k] * dtz;
+}
+
+// Record gradients at one cluster's representative camera -> world mean,
+// world covariance (symmetric, entries xx xy xz yy yz zz) and SH.
+template <int DEG>
+__device__ inline void record_grad(const DevCamera &c, const MeanProj &m, const Cov3 &S, double mx, double my,
+                                   double mz, const float *shc, const GradRec &g, double dmu[3], double dS[6],
+                                   float *dsh)
+{
+    const double *R = c.R;
+    // forward: V = R S R^T, J, Sigma2D (the same expressions as project_full)
+    const double s00 = S.xx, s01 = S.xy, s02 = S.xz, s11 = S.yy, s12 = S.yz, s22 = S.zz;
+    const double a00 = (R[0] * s00 + R[1] * s01) + R[2] * s02;
+    const double a01 = (R[0] * s01 + R[1] * s11) + R[2] * s12;
+    const double a02 = (R[0] * s02 + R[1] * s12) + R[2] * s22;
+    const double a10 = (R[3] * s00 + R[4] * s01) + R[5] * s02;
+    const double a11 = (R[3] * s01 + R[4] * s11) + R[5] * s12;
+    const double a12 = (R[3] * s02 + R[4] * s12) + R[5] * s22;
+    const double a20 = (R[6] * s00 + R[7] * s01) + R[8] * s02;
+    const double a21 = (R[6] * s01 + R[7] * s11) + R[8] * s12;
+    const double a22 = (R[6] * s02 + R[7] * s12) + R[8] * s22;
+    const double v00 = (a00 * R[0] + a01 * R[1]) + a02 * R[2];
+    const double v01 = (a00 * R[3] + a01 * R[4]) + a02 * R[5];
+    const double v02 = (a00 * R[6] + a01 * R[7]) + a02 * R[8];
+    const double v11 = (a10 * R[3] + a11 * R[4]) + a12 * R[5];
+    const double v12 = (a10 * R[6] + a11 * R[7]) + a12 * R[8];
+    const double v20 = (a20 * R[0] + a21 * R[1]) + a22 * R[2];
+    const double v21 = (a20 * R[3] + a21 * R[4]) + a22 * R[5];
+    const double v22 = (a20 * R[6] + a21 * R[7]) + a22 * R[8];
+    const double cxl = m.ux < -c.limx ? -c.limx : (m.ux > c.limx ? c.limx : m.ux);
+    const double cyl = m.uy < -c.limy ? -c.limy : (m.uy > c.limy ? c.limy : m.uy);
+    const double tz = m.tz, tz2 = tz * tz;
+    const double j00 = c.fx / tz, j02 = -(c.fx * cxl) / tz;
+    const double j11 = c.fy / tz, j12 = -(c.fy * cyl) / tz;
+    const double k00 = j00 * v00 + j02 * v20, k01 = j00 * v01 + j02 * v21, k02 = j00 * v02 + j02 * v22;
+    const double k10 = j11 * v01 + j12 * v20, k11 = j11 * v11 + j12 * v21, k12 = j11 * v12 + j12 * v22;
+    const double sa = (k00 * j00 + k02 * j02) + kDilation;
+    const double sb = k01 * j11 + k02 * j12;
+    const double sc = (k11 * j11 + k12 * j12) + kDilation;
+    const double det = sa * sc - sb * sb;
+
+    // A' = h sc/det, beta = -sb/sc, G' = h/sc  ->  d(sa, sb, sc)
+    const double gA = (double)g.a.x * kHalfLog2e, gB = (double)g.a.y, gG = (double)g.a.z * kHalfLog2e;
+    const double id2 = 1.0 / (det * det), isc = 1.0 / sc;
+    const double dsa = -gA * sc * sc * id2;
+    const double dsb = 2.0 * gA * sb * sc * id2 - gB * isc;
+    const double dsc = -gA * sb * sb * id2 + gB * sb * isc * isc - gG * isc * isc;
+    // Sigma2D = J V J^T with the symmetric upstream P = [[dsa, dsb/2], [dsb/2, dsc]]:
+    // dV = J^T P J, dJ = 2 P (J V)
+    const double p00 = dsa, p01 = 0.5 * dsb, p11 = dsc;
+    const double q0 = p00 * j02 + p01 * j12, q1 = p01 * j02 + p11 * j12;
+    const double D00 = j00 * j00 * p00, D01 = j00 * j11 * p01, D02 = j00 * q0;
+    const double D11 = j11 * j11 * p11, D12 = j11 * q1, D22 = j02 * q0 + j12 * q1;
+    const double dj00 = 2.0 * (p00 * k00 + p01 * k10), dj02 = 2.0 * (p00 * k02 + p01 * k12);
+    const double dj11 = 2.0 * (p01 * k01 + p11 * k11), dj12 = 2.0 * (p01 * k02 + p11 * k12);
+    // J -> camera-space mean (the clamped direction passes nothing)
+    double dtz = (-dj00 * c.fx + dj02 * c.fx * cxl - dj11 * c.fy + dj12 * c.fy * cyl) / tz2;
+    double dtx = 0.0, dty = 0.0;
+    if (cxl == m.ux) {
+        const double d = -dj02 * c.fx / tz;
+        dtx += d / tz;
+        dtz -= d * m.tx / tz2;
+    }
+    if (cyl == m.uy) {
+        const double d = -dj12 * c.fy / tz;
+        dty += d / tz;
+        dtz -= d * m.ty / tz2;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dmu[k] += (R[k] * dtx + R[3 + k] * dty) + R[6 + k] * dtz;
+    // V = R S R^T -> dS = R^T D R
+    const double D[9] = {D00, D01, D02, D01, D11, D12, D02, D12, D22};
+    double B[9];  // D R
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) B[r * 3 + k] = (D[r * 3] * R[k] + D[r * 3 + 1] * R[3 + k]) + D[r * 3 + 2] * R[6 + k];
+    auto rtb = [&](int a, int b) { return (R[a] * B[b] + R[3 + a] * B[3 + b]) + R[6 + a] * B[6 + b]; };
+    dS[0] += rtb(0, 0);
+    dS[1] += rtb(0, 1);
+    dS[2] += rtb(0, 2);
+    dS[3] += rtb(1, 1);
+    dS[4] += rtb(1, 2);
+    dS[5] += rtb(2, 2);
+
+    // colour along the direction camera -> mean
+    const float dcol[3] = {g.c.x, g.c.y, g.c.z};
+    if (dcol[0] == 0.0f && dcol[1] == 0.0f && dcol[2] == 0.0f) return;
+    double vx = mx - c.campos[0], vy = my - c.campos[1], vz = mz - c.campos[2];
+    const double dn = sqrt((vx * vx + vy * vy) + vz * vz);
+    vx = vx / dn;
+    vy = vy / dn;
+    vz = vz / dn;
+    double Y[16], Gx[16], Gy[16], Gz[16];
+    sh_basis_grad<DEG>(vx, vy, vz, Y, Gx, Gy, Gz);
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        if (dcol[u] == 0.0f) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc = acc + Y[b] * (double)shc[b * 3 + u];
+        acc = acc + 0.5;
+        if (!(acc > 0.0)) continue;
+        const double dc = dcol[u];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double h = shc[b * 3 + u];
+            dsh[b * 3 + u] += (float)(Y[b] * dc);
+            ex += dc * h * Gx[b];
+            ey += dc * h * Gy[b];
+            ez += dc * h * Gz[b];
+        }
+    }
+    const double dot = (ex * vx + ey * vy) + ez * vz;
+    dmu[0] += (ex - vx * dot) / dn;
+    dmu[1] += (ey - vy * dot) / dn;
+    dmu[2] += (ez - vz * dot) / dn;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) project_backward_kernel(SceneDev sc, const DevCamera *__restrict__ cams,
+                                                               int n_clusters, const int32_t *__restrict__ cluster_cam,
+                                                               int n_views, const int32_t *__restrict__ view_cam,
+                                                               const GradRec *__restrict__ d_rec,
+                                                               const float2 *__restrict__ d_mean2d, SceneGrads out)
+{
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.M) return;
+    const int64_t M = sc.M;
+    GaussIn g;
+    float shc[NB * 3];
+    load_gaussian<DEG>(sc, i, g, shc);
+    const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
+    double dmu[3] = {0.0, 0.0, 0.0}, dS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, dop = 0.0;
+    float dsh[NB * 3];
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) dsh[k] = 0.0f;
+    const bool want_cov = g.finite && g.o >= kAlphaMin;
+    Cov3 S = {};
+    if (want_cov) S = cov3d(g.ls, g.q);
+    if (want_cov) {
+        for (int k = 0; k < n_clusters; ++k) {
+            const GradRec gr = d_rec[(int64_t)k * M + i];
+            if (gr.a.x == 0.0f && gr.a.y == 0.0f && gr.a.z == 0.0f && gr.a.w == 0.0f && gr.c.x == 0.0f &&
+                gr.c.y == 0.0f && gr.c.z == 0.0f)
+                continue;
+            dop += (double)gr.a.w;
+            const DevCamera &c = cams[cluster_cam[k]];
+            const MeanProj m = project_mean(c, mx, my, mz, g.finite);
+            if (m.valid) record_grad<DEG>(c, m, S, mx, my, mz, shc, gr, dmu, dS, dsh);
+        }
+    }
+    for (int v = 0; v < n_views; ++v) {
+        const float2 dm = d_mean2d[(int64_t)v * M + i];
+        if (dm.x == 0.0f && dm.y == 0.0f) continue;
+        const DevCamera &c = cams[view_cam[v]];
+        const MeanProj m = project_mean(c, mx, my, mz, g.finite);
+        if (m.valid) mean_grad(c, m, dm, dmu);
+    }
+    // Sigma = Mq Mq^T with Mq = Rq(q/|q|) diag(exp(log_scale)): dMq = 2 dS Mq
+    double dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
+    if (want_cov) {
+        const double qn = sqrt((((double)g.q[0] * g.q[0] + (double)g.q[1] * g.q[1]) + (double)g.q[2] * g.q[2]) +
+                               (double)g.q[3] * g.q[3]);
+        const double w = g.q[0] / qn, x = g.q[1] / qn, y = g.q[2] / qn, z = g.q[3] / qn;
+        const double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z),       2.0 * (x * z + w * y),
+                              2.0 * (x * y + w * z),       1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                              2.0 * (x * z - w * y),       2.0 * (y * z + w * x),       1.0 - 2.0 * (x * x + y * y)};
+        const double sv[3] = {exp((double)g.ls[0]), exp((double)g.ls[1]), exp((double)g.ls[2])};
+        const double Gm[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        double gR[9];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double ds = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // dMq[a][b] = 2 sum_k G[a][k] Rq[k][b] s_b
+                const double dM = 2.0 * ((Gm[a * 3] * Rq[b] + Gm[a * 3 + 1] * Rq[3 + b]) + Gm[a * 3 + 2] * Rq[6 + b]) * sv[b];
+                gR[a * 3 + b] = dM * sv[b];
+                ds += dM * Rq[a * 3 + b];
+            }
+            dls[b] = ds * sv[b];
+        }
+        // Rq of the unit quaternion (w, x, y, z), grouped by entry pairs
+        const double dw = 2.0 * (x * (gR[7] - gR[5]) + y * (gR[2] - gR[6]) + z * (gR[3] - gR[1]));
+        const double dx = 2.0 * (y * (gR[1] + gR[3]) + z * (gR[2] + gR[6]) + w * (gR[7] - gR[5]) - 2.0 * x * (gR[4] + gR[8]));
+        const double dy = 2.0 * (x * (gR[1] + gR[3]) + z * (gR[5] + gR[7]) + w * (gR[2] - gR[6]) - 2.0 * y * (gR[0] + gR[8]));
+        const double dz = 2.0 * (x * (gR[2] + gR[6]) + y * (gR[5] + gR[7]) + w * (gR[3] - gR[1]) - 2.0 * z * (gR[0] + gR[4]));
+        // through the normalization q / |q|
+        const double proj = ((dw * w + dx * x) + dy * y) + dz * z;
+        dq[0] = (dw - w * proj) / qn;
+        dq[1] = (dx - x * proj) / qn;
+        dq[2] = (dy - y * proj) / qn;
+        dq[3] = (dz - z * proj) / qn;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        out.means[3 * i + k] = (float)dmu[k];
+        out.log_scales[3 * i + k] = (float)dls[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out.quats[4 * i + k] = (float)dq[k];
+    out.opac[i] = (float)dop;
+    float *o = out.sh + (int64_t)NB * 3 * i;
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) o[k] = dsh[k];
+}
+
+hipError_t launch_project_backward(const SceneDev &sc, const DevCamera *cams, int n_clusters,
+                                   const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
+                                   const GradRec *d_rec, const float2 *d_mean2d, const SceneGrads &out,
+                                   hipStream_t s)
+{
+    if (sc.M == 0) return hipSuccess;
+    const dim3 grid((unsigned)((sc.M + 255) / 256)), block(256);
+    switch (sc.deg) {
+    case 0: hipLaunchKernelGGL(project_backward_kernel<0>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, d_rec, d_mean2d, out); break;
+    case 1: hipLaunchKernelGGL(project_backward_kernel<1>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, d_rec, d_mean2d, out); break;
+    case 2: hipLaunchKernelGGL(project_backward_kernel<2>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, d_rec, d_mean2d, out); break;
+    default: hipLaunchKernelGGL(project_backward_kernel<3>, grid, block, 0, s, sc, cams, n_clusters, cluster_cam, n_views, view_cam, d_rec, d_mean2d, out); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace lfr

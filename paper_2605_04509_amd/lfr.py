@@ -69,10 +69,16 @@ class lfr_stats(Structure):
                 ("ms_project", c_float), ("ms_depth_sort", c_float), ("ms_keygen", c_float),
                 ("ms_sort", c_float), ("ms_ranges", c_float), ("ms_blend", c_float),
                 ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64),
-                ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32), ("blend_launches", c_int32)]
+                ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32), ("blend_launches", c_int32),
+                ("ms_bwd_blend", c_float), ("ms_bwd_project", c_float), ("ms_bwd_total", c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class lfr_scene_grads(Structure):
+    _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+                ("sh", c_void_p)]
 
 
 class lfr_tune_result(Structure):
@@ -109,6 +115,7 @@ _SIGS = {
     "lfr_display_referenced_views": (c_int32, [c_void_p, POINTER(c_int32), _P]),
     "lfr_make_view_cone": (c_int32, [POINTER(lfr_view_cone), _P]),
     "lfr_render": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32, POINTER(lfr_render_opts), _P]),
+    "lfr_render_backward": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, POINTER(lfr_scene_grads)]),
     "lfr_render_fullframe_interlace": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32,
                                                  POINTER(lfr_render_opts), c_int32, _P]),
     "lfr_project": (c_int32, [c_void_p, POINTER(lfr_scene), _P, c_int32, c_int32, _P]),
@@ -332,19 +339,90 @@ def make_view_cone(num_views, width, height, radius, span_deg, fov_x_deg=60.0, c
 
 
 def render(ctx: Context, display: Display, scene: DeviceScene, cams, cluster_size=1, remap=True, cull=True,
-           timing=False, background=(0.0, 0.0, 0.0), out=None, count_work=False, first_chunk=0):
+           timing=False, background=(0.0, 0.0, 0.0), out=None, count_work=False, first_chunk=0,
+           save_for_backward=False):
     torch = _torch()
     if out is None:
         out = torch.empty((display.height, display.width, 3), dtype=torch.float32, device=scene.means.device)
     _require_device_f32(out, "out")
     flags = (LFR_REMAP if remap else 0) | (LFR_CULL_UNREFERENCED if cull else 0) | (LFR_TIMING if timing else 0)
-    flags |= LFR_COUNT_WORK if count_work else 0
+    flags |= (LFR_COUNT_WORK if count_work else 0) | (LFR_SAVE_FOR_BACKWARD if save_for_backward else 0)
     opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background), first_chunk, 0)
     ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
     sc = scene.c_struct()
     _check(library().lfr_render(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca), ctypes.byref(opts),
                                 _ptr(out)), ctx.handle)
     return out
+
+
+GRAD_NAMES = ("means", "log_scales", "quats", "opacities", "sh")
+
+
+def render_backward(ctx: Context, display: Display, scene: DeviceScene, grad_out, grads=None):
+    """Gradients of the last ``render(..., save_for_backward=True)`` on
+    ``ctx`` for the image gradient ``grad_out`` ([H, W, 3] float32 device).
+    Returns a dict of tensors shaped like the scene arrays (``grads`` may
+    supply them; every element is overwritten)."""
+    torch = _torch()
+    _require_device_f32(grad_out, "grad_out")
+    if tuple(grad_out.shape) != (display.height, display.width, 3):
+        raise ValueError("grad_out must be [H, W, 3]")
+    if grads is None:
+        grads = {k: torch.empty_like(getattr(scene, k)) for k in GRAD_NAMES}
+    for k in GRAD_NAMES:
+        _require_device_f32(grads[k], f"grads[{k}]")
+        if grads[k].shape != getattr(scene, k).shape:
+            raise ValueError(f"grads[{k}] must have the shape of scene.{k}")
+    g = lfr_scene_grads(*(grads[k].data_ptr() for k in GRAD_NAMES))
+    sc = scene.c_struct()
+    _check(library().lfr_render_backward(ctx.handle, display.handle, ctypes.byref(sc), _ptr(grad_out),
+                                         ctypes.byref(g)), ctx.handle)
+    return grads
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class RenderFunction(torch.autograd.Function):
+        """Forward: lfr_render with LFR_SAVE_FOR_BACKWARD; backward:
+        lfr_render_backward.  The context must not render again before the
+        backward runs (the library refuses with LFR_ERR_INVALID_ARG)."""
+
+        @staticmethod
+        def forward(fctx, means, log_scales, quats, opacities, sh, ctx, display, cams, sh_degree, cluster_size,
+                    remap, cull, background):
+            scene = DeviceScene(means.detach(), log_scales.detach(), quats.detach(), opacities.detach(),
+                                sh.detach(), sh_degree)
+            out = render(ctx, display, scene, cams, cluster_size=cluster_size, remap=remap, cull=cull,
+                         background=background, save_for_backward=True)
+            fctx.lfr = (ctx, display, scene)
+            return out
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            ctx, display, scene = fctx.lfr
+            g = render_backward(ctx, display, scene, grad_out.contiguous())
+            return (g["means"], g["log_scales"], g["quats"], g["opacities"], g["sh"],
+                    None, None, None, None, None, None, None, None)
+
+    return RenderFunction
+
+
+_render_fn = None
+
+
+def render_differentiable(ctx: Context, display: Display, means, log_scales, quats, opacities, sh, sh_degree, cams,
+                          cluster_size=1, remap=True, cull=True, background=(0.0, 0.0, 0.0)):
+    """The interlaced image as a differentiable function of the scene
+    tensors (torch.autograd): forward lfr_render, backward
+    lfr_render_backward."""
+    global _render_fn
+    if _render_fn is None:
+        _render_fn = _autograd_function()
+    ca = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
+    return _render_fn.apply(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacities.contiguous(),
+                            sh.contiguous(), ctx, display, ca, int(sh_degree), int(cluster_size), bool(remap),
+                            bool(cull), tuple(float(b) for b in background))
 
 
 def render_fullframe_interlace(ctx: Context, display: Display, scene: DeviceScene, cams, view_batch=8, cull=True,
