@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--bwd-steps", type=int, default=10)
+    ap.add_argument("--bwd-workload", default="display")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=96)
     ap.add_argument("--tile", default=None, help="WxH tile shape; default: autotuned")
@@ -77,6 +80,65 @@ def measured_traffic(kernel, workload, tile):
             or t.get("source_sha256") != kernel_source_hash()):
         return None
     return t["hbm_bytes_per_launch"]
+
+
+def fwd_bwd(args, torch, lfr, sync):
+    """Forward + backward at the differentiable configuration: the
+    ``display`` workload (200k Gaussians, SH3, 45 views, 1920x1080) on the
+    exact path (cluster size 1); loss = MSE against the same scene with the
+    means perturbed by N(0, 0.01), rendered by the exact path.  A step is the
+    forward (lists kept for the backward), the loss gradient and the
+    backward into all 59 parameters of every Gaussian."""
+    import numpy as np
+    from workloads import get_workload
+    from workloads.cameras import pack_cameras
+    from workloads.scenes import perturb_means
+    w = get_workload(args.bwd_workload)
+    scene = w.make_scene()
+    cams = lfr.cameras_array(pack_cameras(w.cameras()))
+    ctx = lfr.Context(0)
+    ds = lfr.DeviceScene.from_numpy(scene, device="cuda:0")
+    tgt_scene = lfr.DeviceScene.from_numpy(perturb_means(scene, 5, 0.01), device="cuda:0")
+    n_sub = 3 * w.display.width * w.display.height
+    best = None
+    for tile in ((16, 16), (32, 16), (32, 32), (64, 32)):
+        d = lfr.Display(ctx, w.display.with_tile(*tile))
+        target = lfr.render(ctx, d, tgt_scene, cams, cluster_size=1).clone()
+        grads = {k: torch.empty_like(getattr(ds, k)) for k in lfr.GRAD_NAMES}
+
+        def step(timing=False, d=d, target=target, grads=grads):
+            img = lfr.render(ctx, d, ds, cams, cluster_size=1, save_for_backward=True, timing=timing)
+            gout = (img - target).mul_(2.0 / n_sub)
+            lfr.render_backward(ctx, d, ds, gout, grads)
+            return img
+
+        step()
+        t = timed(step, 2, sync)
+        log(f"fwd+bwd tile {tile}: {t * 1e3:.2f} ms")
+        if best is None or t < best[1]:
+            if best is not None:
+                best[0][0].close()
+            best = ((d, target, grads, step, tile), t)
+        else:
+            d.close()
+    (d, target, grads, step, tile), _ = best
+    for _ in range(2):
+        step()
+    sync()
+    # per-stage split from the library's HIP events (separate, untimed run)
+    img = step(timing=True)
+    st = ctx.stats()
+    t = timed(step, args.bwd_steps, sync)
+    fwd = timed(lambda: lfr.render(ctx, d, ds, cams, cluster_size=1, out=img), args.bwd_steps, sync)
+    loss = float(((img - target) ** 2).mean())
+    d.close()
+    ctx.close()
+    return {"ms": t * 1e3, "forward_only_ms": fwd * 1e3, "tile": list(tile), "cluster_size": 1,
+            "workload": (f"{w.name}: {scene.num_gaussians} Gaussians (SH{scene.sh_degree}), "
+                         f"{w.display.num_views} views, {w.display.width}x{w.display.height}, exact path"),
+            "ms_forward_saved": st["ms_total"], "ms_bwd_blend": st["ms_bwd_blend"],
+            "ms_bwd_project": st["ms_bwd_project"], "ms_bwd_total": st["ms_bwd_total"],
+            "pairs": st["pairs"], "loss": loss, "steps": args.bwd_steps}
 
 
 def timed(fn, steps, sync):
@@ -288,6 +350,12 @@ def main():
         result["plain"] = plain
         result["speedup_vs_plain"] = fps / plain["all_views"]["frames_per_s"]
         result["speedup_vs_plain_referenced"] = fps / plain["referenced_views"]["frames_per_s"]
+
+    if not args.no_backward:
+        fb = fwd_bwd(args, torch, lfr, sync)
+        log("fwd+bwd", fb)
+        result["fwd_bwd_ms"] = fb["ms"]
+        result["fwd_bwd"] = fb
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
