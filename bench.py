@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bwd-steps", type=int, default=10)
     ap.add_argument("--bwd-workload", default="display")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-poses", type=int, default=16)
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=96)
     ap.add_argument("--tile", default=None, help="WxH tile shape; default: autotuned")
@@ -139,6 +142,57 @@ def fwd_bwd(args, torch, lfr, sync):
             "ms_forward_saved": st["ms_total"], "ms_bwd_blend": st["ms_bwd_blend"],
             "ms_bwd_project": st["ms_bwd_project"], "ms_bwd_total": st["ms_bwd_total"],
             "pairs": st["pairs"], "loss": loss, "steps": args.bwd_steps}
+
+
+def batched(args, torch, lfr, sync):
+    """The serving batch: three outdoor-style scenes (0.5M, 1M, 3M Gaussians)
+    on 1920x1080/45-view, 2560x1440/64-view and 3840x2160/100-view panels,
+    each seen from 16 head poses (rig offsets U[-0.05, 0.05]^3), cluster size
+    8.  The tile shape of each display is autotuned on its first pose.  A
+    step is one lfr_render_batch call over all 48 frames (planned frames,
+    replayed from captured hipGraphs, one synchronization); the first calls,
+    which plan the slots and capture the graphs, are warm-up."""
+    from workloads.cameras import orbit_rig, pack_cameras
+    from workloads.configs import batched_frames
+    from workloads.scenes import mixture_scene
+    S = 8
+    ctx = lfr.Context(0)
+    frames, tiles, keep = [], [], []
+    for seed_i, m, disp, radius, span, offs in batched_frames(num_poses=args.batch_poses):
+        ds = lfr.DeviceScene.from_numpy(mixture_scene(seed_i, m, 3), device="cuda:0")
+        rig = lambda o: pack_cameras(orbit_rig(disp.num_views, disp.width, disp.height, radius, span, 60.0,
+                                               centre=(0.0, 0.0, radius), rig_offset=tuple(o)))
+        best, _ = lfr.autotune(ctx, disp, ds, rig(offs[0]), cluster_sizes=(S,), reps=1)
+        d = lfr.Display(ctx, disp.with_tile(best["tile_w"], best["tile_h"]))
+        tiles.append([disp.width, disp.height, disp.num_views, best["tile_w"], best["tile_h"], m])
+        keep.append((d, ds))
+        for o in offs:
+            out = torch.empty((disp.height, disp.width, 3), dtype=torch.float32, device="cuda:0")
+            frames.append(lfr.Frame(d, ds, rig(o), out, cluster_size=S))
+    n = len(frames)
+    res = {"frames": n, "cluster_size": S, "displays": tiles}
+    for label, graph in (("graph", True), ("planned", False)):
+        bctx = lfr.Context(0)
+        for _ in range(3):
+            st = lfr.render_batch(bctx, frames, graph=graph)
+        t = timed(lambda: lfr.render_batch(bctx, frames, graph=graph), args.batch_steps, sync)
+        st = lfr.render_batch(bctx, frames, graph=graph)
+        res[label] = {"ms_per_batch": t * 1e3, "frames_per_s": n / t, "last_batch": st}
+        log(f"batch {label}: {t * 1e3:.1f} ms per {n} frames ({n / t:.1f} frames/s) {st}")
+        bctx.close()
+    # the same frames one lfr_render call at a time (one host readback per chunk)
+    def unbatched():
+        for f in frames:
+            lfr.render(ctx, f.display, f.scene, f.cams, cluster_size=S, out=f.out)
+    unbatched()
+    t = timed(unbatched, max(1, args.batch_steps - 1), sync)
+    res["unbatched"] = {"ms_per_batch": t * 1e3, "frames_per_s": n / t}
+    log(f"unbatched: {t * 1e3:.1f} ms per {n} frames ({n / t:.1f} frames/s)")
+    res["frames_per_s"] = res["graph"]["frames_per_s"]
+    for d, ds in keep:
+        d.close()
+    ctx.close()
+    return res
 
 
 def timed(fn, steps, sync):
@@ -272,6 +326,8 @@ def main():
                  "launches_per_frame": bl, "flops_per_launch": flops / bl,
                  "achieved": flops / bl / (blend_ms * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
                  "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"],
+                 "wave_steps": work["wave_steps"], "wave_steps_live": work["wave_steps_live"],
+                 "lane_utilization": work["evals"] / max(1, 64 * work["wave_steps"]),
                  "traffic": measured_traffic("blend_remap_kernel<false>", w.name,
                                                (params.tile_w, params.tile_h))}
     blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
@@ -350,6 +406,10 @@ def main():
         result["plain"] = plain
         result["speedup_vs_plain"] = fps / plain["all_views"]["frames_per_s"]
         result["speedup_vs_plain_referenced"] = fps / plain["referenced_views"]["frames_per_s"]
+
+    if not args.no_batch:
+        result["batched"] = batched(args, torch, lfr, sync)
+        result["batched_frames_per_s"] = result["batched"]["frames_per_s"]
 
     if not args.no_backward:
         fb = fwd_bwd(args, torch, lfr, sync)

@@ -128,6 +128,14 @@ typedef struct {
     float ms_bwd_blend;        /* reverse blend into per-(Gaussian, cluster/view) grads */
     float ms_bwd_project;      /* projection backward into per-Gaussian grads  */
     float ms_bwd_total;
+    /* lfr_render_batch */
+    int32_t batch_frames;      /* frames in the last batch                     */
+    int32_t batch_unplanned;   /* of those, rendered with host synchronization (first use of a frame slot) */
+    int32_t batch_graphs;      /* of those, replayed from a captured hipGraph  */
+    int32_t batch_rerendered;  /* planned frames whose pairs exceeded the plan and were rendered again */
+    /* LFR_COUNT_WORK, remapped blend only */
+    uint64_t wave_steps;       /* wavefront steps (one staged Gaussian for 64 lanes) */
+    uint64_t wave_steps_live;  /* of those, steps where some lane's alpha passed the cutoff */
 } lfr_stats;
 
 /* One projected Gaussian (48 bytes), as returned by lfr_project:
@@ -245,6 +253,39 @@ typedef struct {
  * (final transmittance, end of its blended list) plus its sorted lists. */
 lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
                                const float *grad_out_device, const lfr_scene_grads *grads);
+
+/* ---- batched frames (serving) --------------------------------------------- */
+
+/* One frame of a batch: what lfr_render takes. */
+typedef struct {
+    const lfr_display *display;
+    const lfr_scene *scene;
+    const lfr_camera *host_cams;   /* num_cams == the display's num_views     */
+    int32_t num_cams;
+    lfr_render_opts opts;          /* LFR_SAVE_FOR_BACKWARD, LFR_COUNT_WORK not allowed; LFR_TIMING ignored */
+    float *out_device;             /* float32 [H][W][3] of this frame's display */
+} lfr_frame;
+
+#define LFR_BATCH_GRAPH       1u  /* replay frames from captured hipGraphs      */
+#define LFR_BATCH_TIGHT_PLANS 2u  /* plan exactly the pairs seen (no headroom)  */
+
+/* Render num_frames frames, in order, on the context stream, each exactly as
+ * lfr_render would (same image).  Frame i uses frame slot i of the context.
+ * The first time a slot sees a frame (or after its display, scene arrays,
+ * options or output change) the frame is rendered with lfr_render's
+ * synchronizing path and its per-depth-chunk pair counts become the slot's
+ * plan (x 1.25 + 4096 capacity, exact with LFR_BATCH_TIGHT_PLANS).  Planned
+ * frames run with no host synchronization and no allocation: buffers are
+ * sized by the plan and every kernel reads its counts on the device.  With
+ * LFR_BATCH_GRAPH each planned slot is captured once into a hipGraph and
+ * replayed afterwards (cameras may change between batches; they are uploaded
+ * for all frames in one copy before the frames run).  The call synchronizes
+ * once at the end, checks every planned frame's pair counts against its plan,
+ * and renders any frame that exceeded it again (synchronously) with a new
+ * plan; lfr_stats reports how many frames took each path.  Display, scene
+ * and output buffers of planned slots must stay allocated while the context
+ * keeps the slots (they are rebuilt when a pointer changes). */
+lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames, int32_t num_frames, uint32_t flags);
 
 /* ---- autotuning ------------------------------------------------------------- */
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <numeric>
 
 #include "lfr_internal.h"
@@ -23,7 +24,8 @@ namespace {
 enum Slot {
     kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
-    kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kNumSlots
+    kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
+    kNumSlots
 };
 
 struct Buf {
@@ -56,6 +58,21 @@ struct SavedForward {
     const uint32_t *save_end = nullptr;
 };
 
+// A batch frame slot: the frame it was planned for, its plan (pair capacity
+// per depth chunk) and, with LFR_BATCH_GRAPH, the captured planned frame.
+struct FrameSlot {
+    const void *display = nullptr;
+    uint64_t display_uid = 0;
+    lfr_scene scene{};
+    lfr_render_opts opts{};
+    float *out = nullptr;
+    bool tight = false;
+    std::vector<uint64_t> caps;       // empty: not planned
+    hipGraphExec_t graph = nullptr;
+    uint64_t graph_gen = 0;           // workspace generation the graph was captured with
+    size_t graph_table_off = 0;       // offset of the frame's tables it was captured with
+};
+
 struct lfr_context {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -63,14 +80,21 @@ struct lfr_context {
     std::string err;
     lfr_stats stats{};
     Buf ws[kNumSlots];
+    uint64_t ws_gen = 0;              // bumped whenever a workspace buffer moves
+    bool capturing = false;           // a hipGraph capture is in progress: no allocation
     void *pinned = nullptr;
     size_t pinned_n = 0;
+    void *batch_pinned = nullptr;     // staging of a batch's camera tables
+    size_t batch_pinned_n = 0;
+    hipStream_t cap_stream = nullptr; // non-blocking stream graphs are captured on
+    std::vector<FrameSlot> slots;
     Timer timer;
     SavedForward saved;
 };
 
 struct lfr_display {
     int device = 0;
+    uint64_t uid = 0;                 // unique per display ever created
     int W = 0, H = 0, N = 0, tw = 0, th = 0, TX = 0, TY = 0, T = 0;
     uint16_t *d_V = nullptr;
     uint32_t *d_psi = nullptr;
@@ -121,6 +145,9 @@ lfr_status ws_get(lfr_context *ctx, Slot s, size_t bytes, void **out)
     Buf &b = ctx->ws[s];
     if (bytes == 0) bytes = 1;
     if (b.n < bytes) {
+        if (ctx->capturing)
+            return fail(ctx, LFR_ERR_CAPACITY, "workspace would grow during a graph capture");
+        ++ctx->ws_gen;
         size_t want = bytes + bytes / 8 + 256;
         const uint64_t after = ws_total(ctx) - b.n + want;
         if (ctx->limit && after > ctx->limit) {
@@ -266,16 +293,18 @@ struct DevTables {
             *view_slot = nullptr, *view_cluster = nullptr;
 };
 
-lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camera *cams, const ViewTables &vt,
-                         DevTables *out)
+size_t tables_bytes(const lfr_display *d, const ViewTables &vt)
+{
+    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + vt.cv_list.size() + 2 * d->N;
+    return sizeof(DevCamera) * d->N + n_int * sizeof(int32_t);
+}
+
+// Lay the tables out in host staging h for the device copy at dv.
+void write_tables(const lfr_display *d, const lfr_camera *cams, const ViewTables &vt, void *h, void *dv,
+                  DevTables *out)
 {
     const int N = d->N;
     const size_t cam_bytes = sizeof(DevCamera) * N;
-    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + vt.cv_list.size() + 2 * N;
-    const size_t bytes = cam_bytes + n_int * sizeof(int32_t) + 64;
-    void *h = nullptr, *dv = nullptr;
-    CHK(pinned_get(ctx, bytes, &h));
-    CHK(ws_get(ctx, kTables, bytes, &dv));
     DevCamera *hc = (DevCamera *)h;
     for (int j = 0; j < N; ++j) hc[j] = dev_camera(cams[j], d->W, d->H);
     int32_t *hi = (int32_t *)((char *)h + cam_bytes);
@@ -293,7 +322,17 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
     put(vt.view_slot, &out->view_slot);
     put(vt.view_cluster, &out->view_cluster);
     out->cams = (DevCamera *)dv;
-    HIPCHK(ctx, hipMemcpyAsync(dv, h, cam_bytes + o * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+}
+
+lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camera *cams, const ViewTables &vt,
+                         DevTables *out)
+{
+    const size_t bytes = tables_bytes(d, vt);
+    void *h = nullptr, *dv = nullptr;
+    CHK(pinned_get(ctx, bytes + 64, &h));
+    CHK(ws_get(ctx, kTables, bytes + 64, &dv));
+    write_tables(d, cams, vt, h, dv, out);
+    HIPCHK(ctx, hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, ctx->stream));
     return LFR_OK;
 }
 
@@ -384,6 +423,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive = alive;
     bp.alive_words = (d->TX + 31) / 32;
     bp.items = items;
+    bp.alive_total = nullptr;
     return bp;
 }
 
@@ -396,16 +436,19 @@ struct Totals {
 };
 
 // One depth chunk: pair count -> scan -> (host readback) -> emit -> stable
-// sort on the tile bits -> list ranges.
+// sort on the tile bits -> list ranges.  With cap > 0 (a planned frame) there
+// is no readback: buffers hold cap pairs, the emit, sort and ranges kernels
+// read the count from the device (clamped to cap), and the count is copied to
+// *d_need for the host to check after the frame.
 struct Chunk {
-    uint64_t P = 0;
-    uint32_t alive = 0;
+    uint64_t P = 0;        // pairs (unplanned chunks only)
+    uint32_t alive = 0;    // unsaturated subpixels before the chunk (unplanned only)
     const uint32_t *vals = nullptr;
     uint2 *ranges = nullptr;
 };
 
 lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr, int64_t r0, int64_t len,
-                     Totals *d_tot, Chunk *out)
+                     Totals *d_tot, Chunk *out, uint64_t cap = 0, uint64_t *d_need = nullptr)
 {
     hipStream_t s = ctx->stream;
     Timer &tm = ctx->timer;
@@ -418,15 +461,23 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     const size_t e0 = tm.mark(s);
     HIPCHK(ctx, launch_chunk_count(bp, pr.dks, pr.dvs, r0, len, counts, s));
     HIPCHK(ctx, launch_exclusive_scan(counts, offsets, n, scan_temp, &d_tot->pairs, s));
-    void *h = nullptr;
-    CHK(pinned_get(ctx, sizeof(Totals), &h));
-    HIPCHK(ctx, hipMemcpyAsync(h, d_tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    const Totals ht = *(const Totals *)h;
-    if (ht.pairs >= 0xFFFFFFFFull)
-        return fail(ctx, LFR_ERR_UNSUPPORTED, "%llu Gaussian-tile pairs in one chunk exceed 2^32",
-                    (unsigned long long)ht.pairs);
-    const uint64_t P = ht.pairs;
+    uint64_t P = cap;
+    const uint64_t *dP = nullptr;
+    Totals ht{};
+    if (cap > 0) {
+        dP = &d_tot->pairs;
+        if (d_need) HIPCHK(ctx, launch_record_count(dP, d_need, s));
+    } else {
+        void *h = nullptr;
+        CHK(pinned_get(ctx, sizeof(Totals), &h));
+        HIPCHK(ctx, hipMemcpyAsync(h, d_tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        ht = *(const Totals *)h;
+        if (ht.pairs >= 0xFFFFFFFFull)
+            return fail(ctx, LFR_ERR_UNSUPPORTED, "%llu Gaussian-tile pairs in one chunk exceed 2^32",
+                        (unsigned long long)ht.pairs);
+        P = ht.pairs;
+    }
     uint32_t *pk0, *pv0, *pk1, *pv1;
     void *sort_temp;
     CHK(ws_get_t(ctx, kPairK0, P, &pk0));
@@ -440,7 +491,7 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     tm.span(kStKeygen, e0, e1);
     bool palt = false;
     HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, bp.cluster_bits, bp.cluster_bits + bits_for(
-                                   (int64_t)bp.TX * bp.TY), sort_temp, &palt, s, &tm));
+                                   (int64_t)bp.TX * bp.TY), sort_temp, &palt, s, &tm, dP));
     const uint32_t *keys = palt ? pk1 : pk0;
     const size_t e2 = tm.mark(s);
     tm.span(kStSort, e1, e2);
@@ -448,9 +499,9 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     uint2 *ranges;
     CHK(ws_get_t(ctx, kRanges, n_ranges, &ranges));
     HIPCHK(ctx, launch_fill_u32((uint32_t *)ranges, 0u, 2 * n_ranges, s));
-    HIPCHK(ctx, launch_ranges(keys, (int64_t)P, ranges, s));
+    HIPCHK(ctx, launch_ranges(keys, (int64_t)P, ranges, s, dP));
     tm.span(kStRanges, e2, tm.mark(s));
-    out->P = P;
+    out->P = cap > 0 ? 0 : P;
     out->alive = ht.alive;
     out->vals = palt ? pv1 : pv0;
     out->ranges = ranges;
@@ -570,6 +621,201 @@ lfr_status finish_backward_timing(lfr_context *ctx)
     return LFR_OK;
 }
 
+// How render_frame runs one frame.
+//  - tables: camera tables already on the device (batched frames upload all
+//    frames' tables at once), else they are uploaded here;
+//  - caps (planned frame): pair capacity of every depth chunk.  Nothing is
+//    read back and nothing synchronizes; every chunk runs; each chunk's pair
+//    count is recorded to d_need[chunk] for the caller to compare with caps
+//    afterwards (a count above its cap means the frame must be re-rendered);
+//  - chunk_pairs (unplanned frame): receives each chunk's pair count.
+constexpr int kMaxPlannedChunks = 16;
+constexpr uint64_t kUnplannedChunkCap = 1u << 16;
+struct FrameRun {
+    const DevTables *tables = nullptr;
+    const std::vector<uint64_t> *caps = nullptr;
+    uint64_t *d_need = nullptr;
+    std::vector<uint64_t> *chunk_pairs = nullptr;
+};
+
+// One frame of the subpixel renderer (appendix B.2 algorithm).  Arguments are
+// already validated.  `run` (may be null) selects how it runs: see FrameRun.
+lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
+                        const lfr_camera *host_cams, const lfr_render_opts *opts, float *out_device,
+                        const FrameRun *run)
+{
+    lfr_display *d = const_cast<lfr_display *>(display);
+    const bool planned = run && run->caps;
+    hipStream_t s = ctx->stream;
+    const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
+    const bool remap = (opts->flags & LFR_REMAP) != 0;
+    const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
+    const bool save = (opts->flags & LFR_SAVE_FOR_BACKWARD) != 0;
+    const int S = opts->cluster_size;
+    const int64_t M = scene->num_gaussians;
+    const int64_t nsub = 3ll * d->W * d->H;
+    ctx->stats = lfr_stats{};
+    Timer &tm = ctx->timer;
+    const ViewTables vt = build_tables(d, S, cull);
+    TaskSet *ts = nullptr;
+    CHK(get_layout(ctx, d, S, cull, vt, &ts));
+    tm.reset(!planned && (opts->flags & LFR_TIMING) != 0);
+    const size_t t0 = tm.mark(s);
+    DevTables dt;
+    if (run && run->tables)
+        dt = *run->tables;
+    else
+        CHK(upload_tables(ctx, d, host_cams, vt, &dt));
+    Projected pr;
+    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, &pr));
+
+    // traversal state: unsaturated subpixels per (tile, cluster) list and in
+    // total, the lists' alive bits, per-subpixel (T, C), per-item flags
+    const int words = (d->TX + 31) / 32;
+    const int64_t n_tc = (int64_t)d->T << pr.cbits;
+    uint32_t *tc_alive, *alive_bits;
+    float2 *state;
+    uint8_t *task_alive;
+    Totals *d_tot;
+    CHK(ws_get_t(ctx, kAlive, n_tc, &tc_alive));
+    CHK(ws_get_t(ctx, kAliveBits, (int64_t)vt.n_clusters * d->TY * words, &alive_bits));
+    CHK(ws_get_t(ctx, kState, nsub, &state));
+    CHK(ws_get_t(ctx, kTaskAlive, (size_t)std::max(ts->n, 1) + 4, &task_alive));
+    CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
+    HIPCHK(ctx, launch_copy_u32(tc_alive, ts->d_tc_count, n_tc, s));
+    HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
+    HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
+    HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+
+    BlendParams bp;
+    bp.W = d->W;
+    bp.H = d->H;
+    bp.tw = d->tw;
+    bp.th = d->th;
+    bp.TX = d->TX;
+    bp.M = M;
+    bp.cluster_bits = pr.cbits;
+    bp.V = d->d_V;
+    bp.psi = d->d_psi;
+    bp.view_slot = dt.view_slot;
+    bp.view_cluster = dt.view_cluster;
+    bp.rec = pr.rec;
+    bp.mean2d = pr.mean2d;
+    for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
+    bp.out = out_device;
+    bp.work = nullptr;
+    bp.state = state;
+    bp.task_alive = task_alive;
+    bp.tc_alive = tc_alive;
+    bp.alive_total = &d_tot->alive;
+    if (count) {
+        CHK(ws_get_t(ctx, kWork, 4, &bp.work));
+        HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 8, s));
+    }
+    bp.save_T = nullptr;
+    bp.save_end = nullptr;
+    if (save) {
+        CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
+        CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
+    }
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.cbits, alive_bits, pr.items);
+    if (planned) bin.alive_total = &d_tot->alive;
+
+    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
+    // (one chunk holding every rank when the lists are kept for the backward)
+    int64_t r0 = 0, len = save ? std::max<int64_t>(M, 1)
+                          : opts->first_chunk > 0
+                              ? (int64_t)opts->first_chunk
+                              : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    Chunk saved_chunk;
+    bool blend_ran = false;
+    uint64_t pairs = 0;
+    int chunks = 0;
+    for (int c = 0;; ++c) {
+        len = std::min(len, M - r0);
+        const bool last = r0 + len >= M;
+        Chunk ch;
+        if (planned) {
+            const uint64_t cap = c < (int)run->caps->size() ? (*run->caps)[c] : kUnplannedChunkCap;
+            CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch, std::max<uint64_t>(cap, 1),
+                          run->d_need ? run->d_need + std::min(c, kMaxPlannedChunks - 1) : nullptr));
+        } else {
+            CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch));
+            if (run && run->chunk_pairs) run->chunk_pairs->push_back(ch.P);
+        }
+        saved_chunk = ch;
+        // every subpixel saturated: all outputs written (a planned frame
+        // runs every chunk; its kernels see the saturation on the device)
+        if (!planned && blend_ran && ch.alive == 0) break;
+        ++chunks;
+        pairs += ch.P;
+        if (planned || ch.P > 0 || last) {
+            bp.ranges = ch.ranges;
+            bp.vals = ch.vals;
+            bp.first = blend_ran ? 0 : 1;
+            bp.last = last ? 1 : 0;
+            const size_t e0 = tm.mark(s);
+            if (remap)
+                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
+            else
+                HIPCHK(ctx, launch_blend_rowmajor(bp, s));
+            const size_t e1 = tm.mark(s);
+            tm.span(kStBlend, e0, e1);
+            ++ctx->stats.blend_launches;
+            if (!last) {
+                HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+                tm.span(kStRanges, e1, tm.mark(s));
+            }
+            blend_ran = true;
+        }
+        if (last) break;
+        r0 += len;
+        len *= 4;
+    }
+    tm.span(kStTotal, t0, tm.mark(s));
+    if (save) {
+        SavedForward &sv = ctx->saved;
+        sv.display = d;
+        sv.M = M;
+        sv.deg = scene->sh_degree;
+        sv.timing = (opts->flags & LFR_TIMING) != 0;
+        for (int k = 0; k < 3; ++k) sv.bg[k] = opts->background[k];
+        sv.n_clusters = vt.n_clusters;
+        sv.n_views = vt.n_views;
+        sv.cbits = pr.cbits;
+        sv.cams = dt.cams;
+        sv.cluster_cam = dt.cluster_cam;
+        sv.view_cam = dt.view_cam;
+        sv.view_slot = dt.view_slot;
+        sv.rec = pr.rec;
+        sv.mean2d = pr.mean2d;
+        sv.ranges = saved_chunk.ranges;
+        sv.vals = saved_chunk.vals;
+        sv.tasks = ts->d_tasks;
+        sv.n_tasks = ts->n;
+        sv.save_T = bp.save_T;
+        sv.save_end = bp.save_end;
+        sv.valid = true;
+    }
+    ctx->stats.pairs = pairs;
+    ctx->stats.chunks = chunks;  // blend_launches was counted in the loop
+    ctx->stats.clusters = vt.n_clusters;
+    ctx->stats.views = vt.n_views;
+    ctx->stats.tasks = remap ? ts->n : d->T;
+    ctx->stats.workspace_bytes = ws_total(ctx);
+    if (planned) return LFR_OK;
+    if (count) {
+        unsigned long long w[4] = {0, 0, 0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(w, bp.work, sizeof w, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        ctx->stats.evals = w[0];
+        ctx->stats.blended = w[1];
+        ctx->stats.wave_steps = w[2];
+        ctx->stats.wave_steps_live = w[3];
+    }
+    return finish_timing(ctx);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -599,9 +845,13 @@ void lfr_context_destroy(lfr_context *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (FrameSlot &sl : ctx->slots)
+        if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (Buf &b : ctx->ws)
         if (b.p) (void)hipFree(b.p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->batch_pinned) (void)hipHostFree(ctx->batch_pinned);
     delete ctx;
 }
 
@@ -628,6 +878,7 @@ lfr_status lfr_context_trim(lfr_context *ctx)
         b.p = nullptr;
         b.n = 0;
     }
+    ++ctx->ws_gen;
     return LFR_OK;
 }
 
@@ -672,8 +923,10 @@ static bool tile_shape_ok(int tw, int th) { return tile_ok(tw) && tile_ok(th) &&
 
 static lfr_display *new_display(lfr_context *ctx, int W, int H, int N, int tw, int th)
 {
+    static std::atomic<uint64_t> next_uid{1};
     lfr_display *d = new lfr_display();
     d->device = ctx->device;
+    d->uid = next_uid++;
     d->W = W;
     d->H = H;
     d->N = N;
@@ -846,159 +1099,7 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
 {
     CHK(begin(ctx));
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
-    lfr_display *d = const_cast<lfr_display *>(display);
-    hipStream_t s = ctx->stream;
-    const bool cull = (opts->flags & LFR_CULL_UNREFERENCED) != 0;
-    const bool remap = (opts->flags & LFR_REMAP) != 0;
-    const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
-    const bool save = (opts->flags & LFR_SAVE_FOR_BACKWARD) != 0;
-    const int S = opts->cluster_size;
-    const int64_t M = scene->num_gaussians;
-    const int64_t nsub = 3ll * d->W * d->H;
-    ctx->stats = lfr_stats{};
-    Timer &tm = ctx->timer;
-    const ViewTables vt = build_tables(d, S, cull);
-    TaskSet *ts = nullptr;
-    CHK(get_layout(ctx, d, S, cull, vt, &ts));
-    tm.reset((opts->flags & LFR_TIMING) != 0);
-    const size_t t0 = tm.mark(s);
-    DevTables dt;
-    CHK(upload_tables(ctx, d, host_cams, vt, &dt));
-    Projected pr;
-    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, &pr));
-
-    // traversal state: unsaturated subpixels per (tile, cluster) list and in
-    // total, the lists' alive bits, per-subpixel (T, C), per-item flags
-    const int words = (d->TX + 31) / 32;
-    const int64_t n_tc = (int64_t)d->T << pr.cbits;
-    uint32_t *tc_alive, *alive_bits;
-    float2 *state;
-    uint8_t *task_alive;
-    Totals *d_tot;
-    CHK(ws_get_t(ctx, kAlive, n_tc, &tc_alive));
-    CHK(ws_get_t(ctx, kAliveBits, (int64_t)vt.n_clusters * d->TY * words, &alive_bits));
-    CHK(ws_get_t(ctx, kState, nsub, &state));
-    CHK(ws_get_t(ctx, kTaskAlive, (size_t)std::max(ts->n, 1) + 4, &task_alive));
-    CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
-    HIPCHK(ctx, hipMemcpyAsync(tc_alive, ts->d_tc_count, sizeof(uint32_t) * n_tc, hipMemcpyDeviceToDevice, s));
-    HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
-    HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
-    HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
-
-    BlendParams bp;
-    bp.W = d->W;
-    bp.H = d->H;
-    bp.tw = d->tw;
-    bp.th = d->th;
-    bp.TX = d->TX;
-    bp.M = M;
-    bp.cluster_bits = pr.cbits;
-    bp.V = d->d_V;
-    bp.psi = d->d_psi;
-    bp.view_slot = dt.view_slot;
-    bp.view_cluster = dt.view_cluster;
-    bp.rec = pr.rec;
-    bp.mean2d = pr.mean2d;
-    for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
-    bp.out = out_device;
-    bp.work = nullptr;
-    bp.state = state;
-    bp.task_alive = task_alive;
-    bp.tc_alive = tc_alive;
-    bp.alive_total = &d_tot->alive;
-    if (count) {
-        CHK(ws_get_t(ctx, kWork, 2, &bp.work));
-        HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 4, s));
-    }
-    bp.save_T = nullptr;
-    bp.save_end = nullptr;
-    if (save) {
-        CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
-        CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
-    }
-    const BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.cbits, alive_bits, pr.items);
-
-    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
-    // (one chunk holding every rank when the lists are kept for the backward)
-    int64_t r0 = 0, len = save ? std::max<int64_t>(M, 1)
-                          : opts->first_chunk > 0
-                              ? (int64_t)opts->first_chunk
-                              : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
-    Chunk saved_chunk;
-    bool blend_ran = false;
-    uint64_t pairs = 0;
-    int chunks = 0;
-    for (;;) {
-        len = std::min(len, M - r0);
-        const bool last = r0 + len >= M;
-        Chunk ch;
-        CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch));
-        saved_chunk = ch;
-        if (blend_ran && ch.alive == 0) break;  // every subpixel saturated: all outputs written
-        ++chunks;
-        pairs += ch.P;
-        if (ch.P > 0 || last) {
-            bp.ranges = ch.ranges;
-            bp.vals = ch.vals;
-            bp.first = blend_ran ? 0 : 1;
-            bp.last = last ? 1 : 0;
-            const size_t e0 = tm.mark(s);
-            if (remap)
-                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
-            else
-                HIPCHK(ctx, launch_blend_rowmajor(bp, s));
-            const size_t e1 = tm.mark(s);
-            tm.span(kStBlend, e0, e1);
-            ++ctx->stats.blend_launches;
-            if (!last) {
-                HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
-                tm.span(kStRanges, e1, tm.mark(s));
-            }
-            blend_ran = true;
-        }
-        if (last) break;
-        r0 += len;
-        len *= 4;
-    }
-    tm.span(kStTotal, t0, tm.mark(s));
-    if (save) {
-        SavedForward &sv = ctx->saved;
-        sv.display = d;
-        sv.M = M;
-        sv.deg = scene->sh_degree;
-        sv.timing = (opts->flags & LFR_TIMING) != 0;
-        for (int k = 0; k < 3; ++k) sv.bg[k] = opts->background[k];
-        sv.n_clusters = vt.n_clusters;
-        sv.n_views = vt.n_views;
-        sv.cbits = pr.cbits;
-        sv.cams = dt.cams;
-        sv.cluster_cam = dt.cluster_cam;
-        sv.view_cam = dt.view_cam;
-        sv.view_slot = dt.view_slot;
-        sv.rec = pr.rec;
-        sv.mean2d = pr.mean2d;
-        sv.ranges = saved_chunk.ranges;
-        sv.vals = saved_chunk.vals;
-        sv.tasks = ts->d_tasks;
-        sv.n_tasks = ts->n;
-        sv.save_T = bp.save_T;
-        sv.save_end = bp.save_end;
-        sv.valid = true;
-    }
-    ctx->stats.pairs = pairs;
-    ctx->stats.chunks = chunks;  // blend_launches was counted in the loop
-    ctx->stats.clusters = vt.n_clusters;
-    ctx->stats.views = vt.n_views;
-    ctx->stats.tasks = remap ? ts->n : d->T;
-    ctx->stats.workspace_bytes = ws_total(ctx);
-    if (count) {
-        unsigned long long w[2] = {0, 0};
-        HIPCHK(ctx, hipMemcpyAsync(w, bp.work, sizeof w, hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        ctx->stats.evals = w[0];
-        ctx->stats.blended = w[1];
-    }
-    return finish_timing(ctx);
+    return render_frame(ctx, display, scene, host_cams, opts, out_device, nullptr);
 }
 
 lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
@@ -1269,3 +1370,214 @@ lfr_status lfr_sort_pairs_u64(lfr_context *ctx, uint64_t *keys, uint32_t *vals, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched frames
+// ---------------------------------------------------------------------------
+namespace {
+
+// Number of depth chunks render_frame runs for M Gaussians.
+int chunk_count(int64_t M, int32_t first_chunk)
+{
+    int64_t r0 = 0, len = first_chunk > 0 ? (int64_t)first_chunk
+                                          : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    int n = 0;
+    for (;;) {
+        len = std::min(len, M - r0);
+        ++n;
+        if (r0 + len >= M) return n;
+        r0 += len;
+        len *= 4;
+    }
+}
+
+lfr_status batch_pinned_get(lfr_context *ctx, size_t bytes, void **out)
+{
+    if (ctx->batch_pinned_n < bytes) {
+        if (ctx->batch_pinned) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            HIPCHK(ctx, hipHostFree(ctx->batch_pinned));
+            ctx->batch_pinned = nullptr;
+            ctx->batch_pinned_n = 0;
+        }
+        const size_t want = std::max<size_t>(bytes, 1 << 16);
+        HIPCHK(ctx, hipHostMalloc(&ctx->batch_pinned, want, hipHostMallocDefault));
+        ctx->batch_pinned_n = want;
+    }
+    *out = ctx->batch_pinned;
+    return LFR_OK;
+}
+
+void drop_graph(FrameSlot &sl)
+{
+    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    sl.graph = nullptr;
+}
+
+bool same_frame(const FrameSlot &sl, const lfr_frame &f, bool tight)
+{
+    return sl.display == (const void *)f.display && sl.display_uid == f.display->uid &&
+           memcmp(&sl.scene, f.scene, sizeof(lfr_scene)) == 0 && memcmp(&sl.opts, &f.opts, sizeof(lfr_render_opts)) == 0 &&
+           sl.out == f.out_device && sl.tight == tight;
+}
+
+// Plan from an unplanned render's per-chunk pair counts.
+void set_plan(FrameSlot &sl, const std::vector<uint64_t> &pairs, bool tight)
+{
+    sl.caps.resize(pairs.size());
+    for (size_t c = 0; c < pairs.size(); ++c)
+        sl.caps[c] = tight ? pairs[c] : pairs[c] + pairs[c] / 4 + 4096;
+}
+
+// Capture one planned frame into a graph.  On failure (e.g. the workspace
+// would have to grow) the capture is discarded and *exec stays null.
+lfr_status capture_frame(lfr_context *ctx, const lfr_frame &f, const FrameRun &run, hipGraphExec_t *exec)
+{
+    *exec = nullptr;
+    if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    const hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    const lfr_status st = render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run);
+    ctx->capturing = false;
+    ctx->stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (st != LFR_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        ctx->err.clear();
+        return LFR_OK;
+    }
+    const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        *exec = nullptr;
+        (void)hipGetLastError();
+    }
+    return LFR_OK;
+}
+
+}  // namespace
+
+extern "C" lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames, int32_t num_frames, uint32_t flags)
+{
+    CHK(begin(ctx));
+    if (num_frames < 0 || (num_frames > 0 && !frames))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "bad frame list");
+    if (flags & ~(LFR_BATCH_GRAPH | LFR_BATCH_TIGHT_PLANS)) return fail(ctx, LFR_ERR_INVALID_ARG, "unknown batch flags");
+    for (int i = 0; i < num_frames; ++i) {
+        const lfr_frame &f = frames[i];
+        CHK(check_render_args(ctx, f.display, f.scene, f.host_cams, f.num_cams, &f.opts, f.out_device));
+        if (f.opts.flags & (LFR_SAVE_FOR_BACKWARD | LFR_COUNT_WORK))
+            return fail(ctx, LFR_ERR_INVALID_ARG, "frame %d: LFR_SAVE_FOR_BACKWARD and LFR_COUNT_WORK are not "
+                        "available in a batch", i);
+    }
+    const bool use_graph = (flags & LFR_BATCH_GRAPH) != 0, tight = (flags & LFR_BATCH_TIGHT_PLANS) != 0;
+    hipStream_t s = ctx->stream;
+    if ((int)ctx->slots.size() < num_frames) ctx->slots.resize(num_frames);
+    int n_unplanned = 0, n_graphs = 0, n_rerendered = 0;
+
+    // every frame's camera tables, uploaded in one copy
+    std::vector<ViewTables> vts(num_frames);
+    std::vector<size_t> offs(num_frames);
+    size_t total = 0;
+    for (int i = 0; i < num_frames; ++i) {
+        const lfr_frame &f = frames[i];
+        lfr_display *d = const_cast<lfr_display *>(f.display);
+        const bool cull = (f.opts.flags & LFR_CULL_UNREFERENCED) != 0;
+        vts[i] = build_tables(d, f.opts.cluster_size, cull);
+        TaskSet *ts = nullptr;
+        CHK(get_layout(ctx, d, f.opts.cluster_size, cull, vts[i], &ts));
+        offs[i] = total;
+        total += (tables_bytes(d, vts[i]) + 255) & ~(size_t)255;
+    }
+    void *dtab = nullptr, *htab = nullptr;
+    uint64_t *need = nullptr;
+    CHK(ws_get(ctx, kBatchTables, std::max<size_t>(total, 256), &dtab));
+    CHK(ws_get_t(ctx, kBatchNeed, (size_t)std::max(num_frames, 1) * kMaxPlannedChunks, &need));
+    CHK(batch_pinned_get(ctx, std::max<size_t>(total, 256), &htab));
+    std::vector<DevTables> dts(num_frames);
+    for (int i = 0; i < num_frames; ++i)
+        write_tables(frames[i].display, frames[i].host_cams, vts[i], (char *)htab + offs[i], (char *)dtab + offs[i],
+                     &dts[i]);
+    if (total) HIPCHK(ctx, hipMemcpyAsync(dtab, htab, total, hipMemcpyHostToDevice, s));
+
+    std::vector<int> planned;
+    for (int i = 0; i < num_frames; ++i) {
+        const lfr_frame &f = frames[i];
+        FrameSlot &sl = ctx->slots[i];
+        if (!same_frame(sl, f, tight)) {
+            drop_graph(sl);
+            sl.caps.clear();
+            sl.display = f.display;
+            sl.display_uid = f.display->uid;
+            sl.scene = *f.scene;
+            sl.opts = f.opts;
+            sl.out = f.out_device;
+            sl.tight = tight;
+        }
+        FrameRun run;
+        run.tables = &dts[i];
+        if (sl.caps.empty() || chunk_count(f.scene->num_gaussians, f.opts.first_chunk) > kMaxPlannedChunks) {
+            std::vector<uint64_t> pairs;
+            run.chunk_pairs = &pairs;
+            CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
+            set_plan(sl, pairs, tight);
+            ++n_unplanned;
+            continue;
+        }
+        run.caps = &sl.caps;
+        run.d_need = need + (size_t)i * kMaxPlannedChunks;
+        if (use_graph) {
+            if (sl.graph && (sl.graph_gen != ctx->ws_gen || sl.graph_table_off != offs[i])) drop_graph(sl);
+            if (!sl.graph) {
+                CHK(capture_frame(ctx, f, run, &sl.graph));
+                sl.graph_gen = ctx->ws_gen;
+                sl.graph_table_off = offs[i];
+            }
+            if (sl.graph) {
+                HIPCHK(ctx, hipGraphLaunch(sl.graph, s));
+                ++n_graphs;
+                planned.push_back(i);
+                continue;
+            }
+        }
+        CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
+        planned.push_back(i);
+    }
+
+    // one synchronization: check the planned frames' pair counts
+    std::vector<uint64_t> hneed((size_t)std::max(num_frames, 1) * kMaxPlannedChunks);
+    if (!planned.empty())
+        HIPCHK(ctx, hipMemcpyAsync(hneed.data(), need, hneed.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (int i : planned) {
+        const lfr_frame &f = frames[i];
+        FrameSlot &sl = ctx->slots[i];
+        const int nc = chunk_count(f.scene->num_gaussians, f.opts.first_chunk);
+        bool over = false;
+        for (int c = 0; c < nc; ++c) {
+            const uint64_t cap = c < (int)sl.caps.size() ? sl.caps[c] : kUnplannedChunkCap;
+            over = over || hneed[(size_t)i * kMaxPlannedChunks + c] > std::max<uint64_t>(cap, 1);
+        }
+        if (!over) continue;
+        drop_graph(sl);
+        FrameRun run;
+        run.tables = &dts[i];
+        std::vector<uint64_t> pairs;
+        run.chunk_pairs = &pairs;
+        CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
+        set_plan(sl, pairs, tight);
+        ++n_rerendered;
+    }
+    if (n_rerendered) HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->stats = lfr_stats{};
+    ctx->stats.batch_frames = num_frames;
+    ctx->stats.batch_unplanned = n_unplanned;
+    ctx->stats.batch_graphs = n_graphs;
+    ctx->stats.batch_rerendered = n_rerendered;
+    ctx->stats.workspace_bytes = ws_total(ctx);
+    return LFR_OK;
+}

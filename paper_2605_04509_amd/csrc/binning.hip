@@ -111,6 +111,11 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     const int k = blockIdx.y;
     const bool in = rl < len;
     const int64_t o = (int64_t)k * len + rl;
+    // every subpixel saturated (chunks planned ahead of time): no pairs
+    if (bp.alive_total && *bp.alive_total == 0u) {
+        if (!kEmit && in) counts[o] = 0u;
+        return;
+    }
     const ItemRec *items_k = bp.items + (int64_t)k * bp.M;
     uint32_t i = 0;
     int U = 0;
@@ -172,15 +177,28 @@ __global__ void __launch_bounds__(256) fill_kernel(uint32_t *p, uint32_t v, int6
         p[s] = v;
 }
 
-// [start, end) of every (tile, cluster) list, indexed by the list's key.
-__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ keys, int64_t P, uint2 *ranges)
+__global__ void __launch_bounds__(256) copy_kernel(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src,
+                                                    int64_t n)
 {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        dst[s] = src[s];
+}
+
+// [start, end) of every (tile, cluster) list, indexed by the list's key.  The
+// pair count is P, or min(*dP, P) when dP is given.
+__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ keys, int64_t P_cap,
+                                                      const uint64_t *dP, uint2 *ranges)
+{
+    const int64_t P = dP ? (int64_t)min(*dP, (uint64_t)P_cap) : P_cap;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) ranges[k].x = (uint32_t)p;
     if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (uint32_t)(p + 1);
 }
+
+// dst = *src (a device count recorded for the host to read later).
+__global__ void record_count_kernel(const uint64_t *src, uint64_t *dst) { *dst = *src; }
 
 // alive bit of (cluster k, tile t) = (number of unsaturated subpixels of the
 // (t, k) list) > 0; one thread per 32-bit word of a tile row.
@@ -237,10 +255,25 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s)
+hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s, const uint64_t *dP)
 {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(P)), dim3(256), 0, s, keys, P, ranges);
+    hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(P)), dim3(256), 0, s, keys, P, dP, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)g), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_count(const uint64_t *src, uint64_t *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(record_count_kernel, dim3(1), dim3(1), 0, s, src, dst);
     return hipGetLastError();
 }
 

@@ -26,15 +26,35 @@ struct StepEval {
     float dy, w, ex, raw;  // raw = o 2^-E before the clamp
 };
 
-__device__ __forceinline__ float step_eval(const float4 a, const float2 m, float px, float py, StepEval &s)
+// E of the sample (px, py) for record a = (A', beta, G', o) and mean m.
+__device__ __forceinline__ float step_exponent(const float4 a, const float2 m, float px, float py, StepEval &s)
 {
     const float dx = px - m.x;
     s.dy = py - m.y;
     s.w = fmaf(a.y, s.dy, dx);
-    const float E = fmaf(a.x * s.w, s.w, (a.z * s.dy) * s.dy);
+    return fmaf(a.x * s.w, s.w, (a.z * s.dy) * s.dy);
+}
+
+// alpha = min(0.99, o 2^-E).
+__device__ __forceinline__ float step_alpha_of(float o, float E, StepEval &s)
+{
     s.ex = __builtin_amdgcn_exp2f(-E);
-    s.raw = a.w * s.ex;
+    s.raw = o * s.ex;
     return fminf(kAlphaMax, s.raw);
+}
+
+__device__ __forceinline__ float step_eval(const float4 a, const float2 m, float px, float py, StepEval &s)
+{
+    return step_alpha_of(a.w, step_exponent(a, m, px, py, s), s);
+}
+
+// A bound on E beyond which alpha = o 2^-E is certainly below the 1/255
+// cutoff: log2(255 o) + 0.01 (there alpha <= 2^-0.01 / 255 = 0.993 / 255; the
+// margin dwarfs the float32 error of exp2, of log2 and of the product).  -inf
+// for o = 0.  Used only to skip evaluations whose outcome is already known.
+__device__ __forceinline__ float cutoff_exponent(float o)
+{
+    return __builtin_amdgcn_logf(255.0f * o) + 0.01f;
 }
 
 __device__ __forceinline__ float step_alpha(const float4 a, const float2 m, float px, float py)
@@ -72,15 +92,23 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 
 // One 64-lane wavefront per task: up to 64 subpixels of one tile and one
 // cluster, in Psi order.  Gaussians of the (tile, cluster) list are staged
-// 64 at a time into LDS (record + the mean for each distinct view of the
-// wavefront; the next batch is fetched into registers while the current one
-// is evaluated), then every lane walks the batch.  The walk is branch-free:
-// a lane that has stopped keeps executing with its updates masked by selects,
-// and the wavefront leaves as soon as all of its lanes have stopped (checked
-// every 16 Gaussians).  Batches are padded to a multiple of 4 with
-// zero-opacity entries, whose alpha is 0 and never passes the cutoff.
-// kSave (single-chunk renders) also writes each subpixel's final T and the
-// end of its blended list for the backward.
+// 64 at a time into LDS (record, colour, cutoff exponent and the mean for
+// each distinct view of the wavefront; the next batch is fetched into
+// registers while the current one is evaluated), then every lane walks the
+// batch.  The walk is branch-free per lane: a lane that has stopped keeps
+// executing with its updates masked by selects, and the wavefront leaves as
+// soon as all of its lanes have stopped (checked every 16 Gaussians).  A step
+// in which no unfinished lane is within the cutoff exponent of the Gaussian
+// is skipped as a whole (nothing would change).  Batches are padded to a
+// multiple of 4 with zero-opacity entries, which never pass the cutoff.
+//
+// A lane that stops folds the background into its colour, C + T bg (the same
+// operations as the final write), and sets T = 0: afterwards T (1 - alpha)
+// can never pass the stop test, so T = 0 is its "finished" state, here and in
+// the saved per-subpixel state between depth chunks.  The output C + T bg is
+// then C + 0 = C, the same value as writing C + T bg at the stop.
+// kSave (single-chunk renders) also writes each subpixel's final T (before
+// the fold) and the end of its blended list for the backward.
 template <bool kCount, bool kSave>
 __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
                                                           int n_tasks, int per)
@@ -104,6 +132,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     const uint32_t y = pix / (uint32_t)bp.W;
     const uint32_t x = pix - y * (uint32_t)bp.W;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float bgu = bp.bg[u];
 
     // distinct views of this wavefront (Psi is sorted by view inside a tile)
     const int jprev = __shfl_up(j, 1, 64);
@@ -117,10 +146,15 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     const uint2 range = bp.ranges[list];
     const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
     float T = 1.0f, C = 0.0f;
-    bool done = !active;
-    if (!bp.first && active) load_state(bp, at, T, C, done);
-    const bool was_done = done;
-    unsigned long long n_eval = 0, n_blend = 0;
+    if (!bp.first && active) {
+        const float2 st = bp.state[at];
+        T = st.x;
+        C = st.y;
+    }
+    if (!active) T = 0.0f;
+    const bool was_done = T == 0.0f;
+    float Tsave = T;
+    unsigned long long n_eval = 0, n_blend = 0, n_steps = 0, n_live = 0;
     uint32_t endp = 0;
     __syncthreads();
     int slots[kMaxWaveViews];
@@ -145,8 +179,9 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
             for (int q = 0; q < kMaxWaveViews; ++q)
                 if (q < n_runs) gm[q] = sanitize_mean(bp.mean2d[(int64_t)slots[q] * bp.M + i]);
         }
+        gc.w = cutoff_exponent(ga.w);
     };
-    if (__ballot(!done) != 0 && range.x < range.y) {
+    if (__ballot(T > 0.0f) != 0 && range.x < range.y) {
         fetch(range.x);
         for (uint32_t base = range.x; base < range.y; base += kWave) {
             s_a[lane] = ga;
@@ -160,39 +195,59 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
             const int nb4 = (nb + 3) & ~3;
             for (int g0 = 0; g0 < nb4; g0 += 16) {
                 const int g1 = min(g0 + 16, nb4);
-#pragma unroll 4
-                for (int g = g0; g < g1; ++g) {
-                    const float alpha = step_alpha(s_a[g], s_mu[my_run][g], px, py);
-                    const float Tn = T * (1.0f - alpha);
-                    const bool pass = !done && alpha >= kAlphaMin;
-                    const bool take = pass && Tn >= kTStop;
-                    if (kCount) {
-                        n_eval += (!done && g < nb) ? 1u : 0u;
-                        n_blend += take ? 1u : 0u;
+                // groups of 4 steps with a constant-trip inner loop, so the
+                // steps unroll despite the wavefront votes inside them
+                for (int g4 = g0; g4 < g1; g4 += 4) {
+#pragma unroll
+                    for (int gk = 0; gk < 4; ++gk) {
+                        const int g = g4 + gk;
+                        const float4 a = s_a[g];
+                        const float thr = s_c[g * 4 + 3];
+                        StepEval st;
+                        const float E = step_exponent(a, s_mu[my_run][g], px, py, st);
+                        if (kCount) {
+                            n_eval += (T > 0.0f && g < nb) ? 1u : 0u;
+                            n_steps += lane == 0 ? 1u : 0u;
+                        }
+                        // no unfinished lane within the cutoff: nothing changes
+                        if (__ballot((T > 0.0f) & (E <= thr)) == 0) continue;
+                        const float alpha = step_alpha_of(a.w, E, st);
+                        const float Tn = T * (1.0f - alpha);
+                        const bool pass = alpha >= kAlphaMin;
+                        const bool take = pass & (Tn >= kTStop);
+                        const bool stop = pass & !take & (T > 0.0f);
+                        if (kCount) {
+                            n_blend += take ? 1u : 0u;
+                            n_live += (lane == 0 && __ballot(pass & (T > 0.0f)) != 0) ? 1u : 0u;
+                        }
+                        const float Cb = C + T * bgu;
+                        C = take ? fmaf(s_c[g * 4 + u] * alpha, T, C) : (stop ? Cb : C);
+                        if (kSave) {
+                            endp = take ? base + (uint32_t)g + 1u : endp;
+                            Tsave = stop ? T : (take ? Tn : Tsave);
+                        }
+                        T = take ? Tn : (stop ? 0.0f : T);
                     }
-                    C = take ? fmaf(s_c[g * 4 + u] * alpha, T, C) : C;
-                    T = take ? Tn : T;
-                    if (kSave) endp = take ? base + (uint32_t)g + 1u : endp;
-                    done = done || (pass && !take);
                 }
-                if (__ballot(!done) == 0) break;
+                if (__ballot(T > 0.0f) == 0) break;
             }
-            if (__ballot(!done) == 0) break;
+            if (__ballot(T > 0.0f) == 0) break;
             __syncthreads();
         }
     }
+    const bool done = T == 0.0f;
     const uint64_t newly = __ballot(active && done && !was_done);
     const bool all_done = __ballot(!done) == 0;
     if (all_done || bp.last) {
         if (active) {
-            bp.out[p] = C + T * bp.bg[u];
+            bp.out[p] = C + T * bgu;
             if (kSave) {
-                bp.save_T[p] = T;
+                bp.save_T[p] = Tsave;
                 bp.save_end[p] = endp;
             }
         }
     } else if (active) {
-        bp.state[at] = make_float2(done ? -T : T, C);
+        bp.state[at] = make_float2(T, C);
     }
     if (lane == 0) {
         if (all_done) bp.task_alive[ti] = 0;
@@ -205,6 +260,8 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     if (kCount) {
         add_work(bp.work, n_eval);
         add_work(bp.work + 1, n_blend);
+        add_work(bp.work + 2, n_steps);
+        add_work(bp.work + 3, n_live);
     }
 }
 
@@ -443,7 +500,8 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
         const int nb = (int)(top - b0);
         if (lane < nb) {
             const uint32_t i = bp.vals[b0 + lane];
-            const GaussRec g = rec[i];
+            GaussRec g = rec[i];
+            g.c.w = cutoff_exponent(g.a.w);
             s_a[lane] = g.a;
             *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
             s_i[lane] = i;
@@ -455,8 +513,11 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
         for (int g = nb - 1; g >= 0; --g) {
             const float4 a = s_a[g];
             StepEval st;
-            const float alpha = step_eval(a, s_mu[my_run][g], px, py, st);
-            const bool on = b0 + (uint32_t)g < end && alpha >= kAlphaMin;
+            const float E = step_exponent(a, s_mu[my_run][g], px, py, st);
+            const bool in_list = b0 + (uint32_t)g < end;
+            if (__ballot(in_list && E <= s_c[g * 4 + 3]) == 0) continue;
+            const float alpha = step_alpha_of(a.w, E, st);
+            const bool on = in_list && alpha >= kAlphaMin;
             if (__ballot(on) == 0) continue;
             const float c = s_c[g * 4 + u];
             const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);

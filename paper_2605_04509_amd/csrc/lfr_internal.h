@@ -204,10 +204,11 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, v
 // between (k0, v0) and (k1, v1).  Returns in *result_in_alt whether the
 // sorted data ended in (k1, v1).
 size_t sort_temp_bytes(int64_t n);
-// With a timer, every scatter launch is recorded as a kStScatter span.
+// With a timer, every scatter launch is recorded as a kStScatter span.  With
+// dn, the count is min(*dn, n) read on the device (n sizes the grid and temp).
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s,
-                          Timer *tm = nullptr);
+                          Timer *tm = nullptr, const uint64_t *dn = nullptr);
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
 
@@ -221,6 +222,7 @@ struct BinParams {
     const uint32_t *alive;    // [K'][TY][alive_words] bit per (cluster, tile) list still needed
     int alive_words;          // 32-bit words per tile row
     const ItemRec *items;     // [K'][M]
+    const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
 };
 hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
                               int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
@@ -228,7 +230,11 @@ hipError_t launch_chunk_emit(const BinParams &bp, const uint64_t *dkey_sorted, c
                              int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs,
                              uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s);
+// With dP, the pair count is min(*dP, P) read on the device (P sizes the grid).
+hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s,
+                         const uint64_t *dP = nullptr);
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
+hipError_t launch_record_count(const uint64_t *src, uint64_t *dst, hipStream_t s);
 hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
                              int cluster_bits, uint32_t *bits, hipStream_t s);
 hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,

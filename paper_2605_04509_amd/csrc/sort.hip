@@ -13,10 +13,21 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kSortWaves = kSortBlock / 64;
 
-template <typename K>
-__global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restrict__ keys, int64_t n, int shift,
-                                                                uint32_t mask, uint32_t *hist, int64_t nb)
+// The element count is n, or min(*dn, n) when dn is given (a count known only
+// on the device; the grid is sized for n).
+__device__ __forceinline__ int64_t sort_count(int64_t n, const uint64_t *dn)
 {
+    if (!dn) return n;
+    const uint64_t d = *dn;
+    return d < (uint64_t)n ? (int64_t)d : n;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restrict__ keys, int64_t n_cap,
+                                                                const uint64_t *dn, int shift, uint32_t mask,
+                                                                uint32_t *hist, int64_t nb)
+{
+    const int64_t n = sort_count(n_cap, dn);
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -41,10 +52,11 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                                    K *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                                   int64_t n, int shift, uint32_t mask,
-                                                                   const uint32_t *__restrict__ offs,
+                                                                   int64_t n_cap, const uint64_t *dn, int shift,
+                                                                   uint32_t mask, const uint32_t *__restrict__ offs,
                                                                    const uint32_t *__restrict__ hist, int64_t nb)
 {
+    const int64_t n = sort_count(n_cap, dn);
     constexpr int kPerWave = kSortTile / kSortWaves;  // 1024
     constexpr int kIt = kPerWave / 64;                // 16
     __shared__ K s_key[kSortTile];
@@ -144,7 +156,8 @@ size_t sort_temp_bytes(int64_t n)
 
 template <typename K>
 static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                                  void *temp, bool *in_alt, hipStream_t s, Timer *tm = nullptr)
+                                  void *temp, bool *in_alt, hipStream_t s, Timer *tm = nullptr,
+                                  const uint64_t *dn = nullptr)
 {
     *in_alt = false;
     if (n <= 1 || b1 <= b0) return hipSuccess;
@@ -158,13 +171,13 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
     for (int shift = b0; shift < b1; shift += 8) {
         const int bits = (b1 - shift) < 8 ? (b1 - shift) : 8;
         const uint32_t mask = (1u << bits) - 1u;
-        hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, n, shift, mask,
-                           hist, nb);
+        hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, n, dn, shift,
+                           mask, hist, nb);
         hipError_t e = launch_exclusive_scan(hist, offs, nh, stemp, nullptr, s);
         if (e != hipSuccess) return e;
         const size_t ea = tm ? tm->mark(s) : 0;
         hipLaunchKernelGGL(sort_scatter_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, vi, ko, vo, n,
-                           shift, mask, offs, hist, nb);
+                           dn, shift, mask, offs, hist, nb);
         if (tm) tm->span(kStScatter, ea, tm->mark(s));
         K *tk = ki;
         ki = ko;
@@ -178,9 +191,9 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
 }
 
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s, Timer *tm)
+                          void *temp, bool *in_alt, hipStream_t s, Timer *tm, const uint64_t *dn)
 {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm);
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm, dn);
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,

@@ -70,10 +70,21 @@ class lfr_stats(Structure):
                 ("ms_sort", c_float), ("ms_ranges", c_float), ("ms_blend", c_float),
                 ("ms_total", c_float), ("evals", c_uint64), ("blended", c_uint64),
                 ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32), ("blend_launches", c_int32),
-                ("ms_bwd_blend", c_float), ("ms_bwd_project", c_float), ("ms_bwd_total", c_float)]
+                ("ms_bwd_blend", c_float), ("ms_bwd_project", c_float), ("ms_bwd_total", c_float),
+                ("batch_frames", c_int32), ("batch_unplanned", c_int32), ("batch_graphs", c_int32),
+                ("batch_rerendered", c_int32), ("wave_steps", c_uint64), ("wave_steps_live", c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class lfr_frame(Structure):
+    _fields_ = [("display", c_void_p), ("scene", POINTER(lfr_scene)), ("host_cams", c_void_p),
+                ("num_cams", c_int32), ("opts", lfr_render_opts), ("out_device", c_void_p)]
+
+
+LFR_BATCH_GRAPH = 1
+LFR_BATCH_TIGHT_PLANS = 2
 
 
 class lfr_scene_grads(Structure):
@@ -115,6 +126,7 @@ _SIGS = {
     "lfr_display_referenced_views": (c_int32, [c_void_p, POINTER(c_int32), _P]),
     "lfr_make_view_cone": (c_int32, [POINTER(lfr_view_cone), _P]),
     "lfr_render": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32, POINTER(lfr_render_opts), _P]),
+    "lfr_render_batch": (c_int32, [c_void_p, POINTER(lfr_frame), c_int32, c_uint32]),
     "lfr_render_backward": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, POINTER(lfr_scene_grads)]),
     "lfr_render_fullframe_interlace": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32,
                                                  POINTER(lfr_render_opts), c_int32, _P]),
@@ -353,6 +365,39 @@ def render(ctx: Context, display: Display, scene: DeviceScene, cams, cluster_siz
     _check(library().lfr_render(ctx.handle, display.handle, ctypes.byref(sc), ca, len(ca), ctypes.byref(opts),
                                 _ptr(out)), ctx.handle)
     return out
+
+
+class Frame:
+    """One frame of a batch: lfr_render's arguments."""
+
+    def __init__(self, display: Display, scene: DeviceScene, cams, out, cluster_size=1, remap=True, cull=True,
+                 background=(0.0, 0.0, 0.0), first_chunk=0):
+        _require_device_f32(out, "out")
+        if tuple(out.shape) != (display.height, display.width, 3):
+            raise ValueError("out must be [H, W, 3] of the frame's display")
+        self.display, self.scene, self.out = display, scene, out
+        self.cams = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
+        flags = (LFR_REMAP if remap else 0) | (LFR_CULL_UNREFERENCED if cull else 0)
+        self.opts = lfr_render_opts(cluster_size, flags, (c_float * 3)(*background), first_chunk, 0)
+
+    def set_cameras(self, cams):
+        self.cams = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
+
+
+def render_batch(ctx: Context, frames, graph=True, tight_plans=False):
+    """Render a list of :class:`Frame` with lfr_render_batch (one host
+    synchronization at the end; planned frames replayed from hipGraphs with
+    ``graph``).  Returns the batch counters of lfr_stats."""
+    n = len(frames)
+    scenes = [f.scene.c_struct() for f in frames]          # kept alive for the call
+    arr = (lfr_frame * max(n, 1))()
+    for i, f in enumerate(frames):
+        arr[i] = lfr_frame(f.display.handle.value, ctypes.pointer(scenes[i]), ctypes.addressof(f.cams), len(f.cams),
+                           f.opts, f.out.data_ptr())
+    flags = (LFR_BATCH_GRAPH if graph else 0) | (LFR_BATCH_TIGHT_PLANS if tight_plans else 0)
+    _check(library().lfr_render_batch(ctx.handle, arr, n, flags), ctx.handle)
+    st = ctx.stats()
+    return {k: st[k] for k in ("batch_frames", "batch_unplanned", "batch_graphs", "batch_rerendered")}
 
 
 GRAD_NAMES = ("means", "log_scales", "quats", "opacities", "sh")

@@ -1,0 +1,187 @@
+"""Batched frames (lfr_render_batch): every path a frame can take -- first use
+(synchronizing, builds the plan), planned (no host synchronization), replayed
+from a captured hipGraph, re-rendered after its pairs exceeded the plan --
+must give exactly the image lfr_render gives, which the forward parity tests
+check against the oracle.  One frame is also checked against the oracle
+directly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._parity import colour_bound, compare
+from workloads import DisplayParams, Rational
+from workloads.cameras import orbit_rig, pack_cameras
+from workloads.scenes import mixture_scene
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_04509_amd import lfr
+    ctx = lfr.Context(0)
+    yield lfr, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+# three panels of different shapes (one with ragged tiles), three scenes
+PANELS = [
+    (DisplayParams(256, 144, 16, Rational(1, 6), Rational(5, 1), tile_w=16, tile_h=16), 4000, 4, True),
+    (DisplayParams(320, 180, 24, Rational(1, 6), Rational(5, 1), tile_w=32, tile_h=16), 9000, 8, True),
+    (DisplayParams(200, 120, 10, Rational(1, 5), Rational(31, 5), tile_w=16, tile_h=32), 6000, 1, False),
+]
+
+
+def _rig(p, offset):
+    return pack_cameras(orbit_rig(p.num_views, p.width, p.height, 12.0, 50.0, 60.0, centre=(0.0, 0.0, 12.0),
+                                  rig_offset=offset))
+
+
+def _setup(lfr, ctx, poses=3, seed=9):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frames, ref_args = [], []
+    displays, scenes = [], []
+    for k, (p, m, S, remap) in enumerate(PANELS):
+        d = lfr.Display(ctx, p)
+        sc = mixture_scene(41 + k, m, 3)
+        ds = lfr.DeviceScene.from_numpy(sc, device="cuda:0")
+        displays.append(d)
+        scenes.append((sc, ds))
+        for _ in range(poses):
+            cams = _rig(p, tuple(rng.uniform(-0.05, 0.05, 3)))
+            out = torch.zeros((p.height, p.width, 3), device="cuda:0")
+            frames.append(lfr.Frame(d, ds, cams, out, cluster_size=S, remap=remap))
+            ref_args.append((d, ds, S, remap, p, sc))
+    return frames, ref_args, displays, scenes
+
+
+def _reference(lfr, ctx, frames, ref_args):
+    refs = []
+    for f, (d, ds, S, remap, p, sc) in zip(frames, ref_args):
+        refs.append(lfr.render(ctx, d, ds, f.cams, cluster_size=S, remap=remap).clone())
+    torch.cuda.synchronize()
+    return refs
+
+
+def _check_equal(frames, refs):
+    for i, (f, r) in enumerate(zip(frames, refs)):
+        assert torch.equal(f.out, r), f"frame {i} differs"
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_individual_renders(lib, graph):
+    lfr, ctx = lib
+    bctx = lfr.Context(0)
+    frames, ref_args, displays, scenes = _setup(lfr, ctx)
+    refs = _reference(lfr, ctx, frames, ref_args)
+    n = len(frames)
+    say("batch of", n, "frames, graph", graph)
+    st = lfr.render_batch(bctx, frames, graph=graph)
+    torch.cuda.synchronize()
+    assert st["batch_frames"] == n and st["batch_unplanned"] == n
+    _check_equal(frames, refs)
+    seen_graphs = 0
+    for rep in range(3):
+        for f in frames:
+            f.out.zero_()
+        st = lfr.render_batch(bctx, frames, graph=graph)
+        torch.cuda.synchronize()
+        say(" repeat", rep, st)
+        assert st["batch_unplanned"] == 0
+        seen_graphs = max(seen_graphs, st["batch_graphs"])
+        _check_equal(frames, refs)
+    if graph:
+        assert seen_graphs == n
+    else:
+        assert seen_graphs == 0
+    # new head poses: cameras change, slots keep their plans (and graphs)
+    rng = np.random.Generator(np.random.PCG64(123))
+    for f, (d, ds, S, remap, p, sc) in zip(frames, ref_args):
+        f.set_cameras(_rig(p, tuple(rng.uniform(-0.05, 0.05, 3))))
+        f.out.zero_()
+    refs = _reference(lfr, ctx, frames, ref_args)
+    st = lfr.render_batch(bctx, frames, graph=graph)
+    torch.cuda.synchronize()
+    say(" new poses", st)
+    assert st["batch_unplanned"] == 0
+    _check_equal(frames, refs)
+    bctx.close()
+    for d in displays:
+        d.close()
+
+
+def test_tight_plans_overflow_is_rerendered(lib):
+    lfr, ctx = lib
+    bctx = lfr.Context(0)
+    frames, ref_args, displays, scenes = _setup(lfr, ctx, poses=2)
+    lfr.render_batch(bctx, frames, graph=True, tight_plans=True)
+    lfr.render_batch(bctx, frames, graph=True, tight_plans=True)
+    # move every rig well away from its planned pose: with exact plans some
+    # depth chunks need more pairs than planned
+    rng = np.random.Generator(np.random.PCG64(7))
+    for f, (d, ds, S, remap, p, sc) in zip(frames, ref_args):
+        f.set_cameras(_rig(p, tuple(rng.uniform(-0.6, 0.6, 3))))
+        f.out.zero_()
+    refs = _reference(lfr, ctx, frames, ref_args)
+    st = lfr.render_batch(bctx, frames, graph=True, tight_plans=True)
+    torch.cuda.synchronize()
+    say("tight plans after a pose change", st)
+    assert st["batch_rerendered"] > 0
+    _check_equal(frames, refs)
+    # the re-rendered slots have new plans: the next batch is planned again
+    for f in frames:
+        f.out.zero_()
+    st = lfr.render_batch(bctx, frames, graph=True, tight_plans=True)
+    torch.cuda.synchronize()
+    _check_equal(frames, refs)
+    bctx.close()
+    for d in displays:
+        d.close()
+
+
+def test_batch_frame_against_oracle(lib):
+    lfr, ctx = lib
+    bctx = lfr.Context(0)
+    frames, ref_args, displays, scenes = _setup(lfr, ctx, poses=1)
+    for _ in range(3):
+        lfr.render_batch(bctx, frames, graph=True)
+    torch.cuda.synchronize()
+    f, (d, ds, S, remap, p, sc) = frames[1], ref_args[1]
+    V = oracle.view_map(p)
+    rng = np.random.Generator(np.random.PCG64(5))
+    samples = np.sort(rng.choice(V.size, 3000, replace=False))
+    cams = np.frombuffer(bytes(f.cams), dtype=np.float32).reshape(-1, 16)
+    ref, flags, tflag = oracle.render_subpixels(sc, cams, p, V, S, samples)
+    got = f.out.cpu().numpy().reshape(-1)[samples]
+    say("batch frame vs oracle, S", S)
+    compare(got, ref, flags, tflag, colour_bound(sc), label='batch frame')
+    bctx.close()
+    for d in displays:
+        d.close()
+
+
+def test_batch_errors_and_empty(lib):
+    lfr, ctx = lib
+    import ctypes
+    say("batch error paths")
+    assert lfr.render_batch(ctx, [])["batch_frames"] == 0
+    frames, ref_args, displays, scenes = _setup(lfr, ctx, poses=1)
+    frames[0].opts.flags |= lfr.LFR_SAVE_FOR_BACKWARD
+    with pytest.raises(lfr.LfrError):
+        lfr.render_batch(ctx, frames)
+    rc = lfr.library().lfr_render_batch(ctx.handle, None, -1, 0)
+    assert rc == lfr.LFR_ERR_INVALID_ARG
+    for d in displays:
+        d.close()
