@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--bwd-steps", type=int, default=10)
     ap.add_argument("--bwd-workload", default="display")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true")
     ap.add_argument("--batch-poses", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,6 +143,54 @@ def fwd_bwd(args, torch, lfr, sync):
             "ms_forward_saved": st["ms_total"], "ms_bwd_blend": st["ms_bwd_blend"],
             "ms_bwd_project": st["ms_bwd_project"], "ms_bwd_total": st["ms_bwd_total"],
             "pairs": st["pairs"], "loss": loss, "steps": args.bwd_steps}
+
+
+def paper_shapes(args, torch, lfr, sync):
+    """The paper's two display shapes on the 3M-Gaussian scene: 71 views over
+    53 degrees at 3840x2160 with reuse groups of 18, and 63 views over 53
+    degrees at 1440x2560 with groups of 16.  For each: reuse + remap, the exact
+    path (S = 1, remap), and the plain full-frame-then-interlace baseline over
+    all views at its best view batch; tile shapes autotuned."""
+    from workloads import get_workload
+    from workloads.cameras import pack_cameras
+    res = {}
+    for name, S in (("landscape71", 18), ("portrait63", 16)):
+        w = get_workload(name)
+        ctx = lfr.Context(0)
+        ds = lfr.DeviceScene.from_numpy(w.make_scene(), device="cuda:0")
+        cams = lfr.cameras_array(pack_cameras(w.cameras()))
+        out = torch.empty((w.display.height, w.display.width, 3), dtype=torch.float32, device="cuda:0")
+        r = {"display": [w.display.width, w.display.height, w.display.num_views], "span_deg": w.span_deg}
+        for label, cs in (("reuse+remap", S), ("exact", 1)):
+            best, _ = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(cs,), reps=1)
+            d = lfr.Display(ctx, w.display.with_tile(best["tile_w"], best["tile_h"]))
+            fn = lambda: lfr.render(ctx, d, ds, cams, cluster_size=cs, out=out)
+            fn()
+            t = timed(fn, 5, sync)
+            r[label] = {"cluster_size": cs, "tile": [best["tile_w"], best["tile_h"]], "ms": t * 1e3,
+                        "frames_per_s": 1.0 / t}
+            if label == "exact":
+                plain = None
+                for vb in (18, 36):
+                    fp = lambda vb=vb: lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=vb, out=out,
+                                                                      tile=32)
+                    try:
+                        fp()
+                    except lfr.LfrError as e:
+                        log(f"{name} plain batch {vb}: {e}")
+                        continue
+                    tp = timed(fp, 1, sync)
+                    if plain is None or tp < plain[1]:
+                        plain = (vb, tp)
+                if plain:
+                    r["plain"] = {"view_batch": plain[0], "ms": plain[1] * 1e3, "frames_per_s": 1.0 / plain[1]}
+            d.close()
+        if "plain" in r:
+            r["speedup_vs_plain"] = r["plain"]["ms"] / r["reuse+remap"]["ms"]
+        log(name, r)
+        res[name] = r
+        ctx.close()
+    return res
 
 
 def batched(args, torch, lfr, sync):
@@ -406,6 +455,9 @@ def main():
         result["plain"] = plain
         result["speedup_vs_plain"] = fps / plain["all_views"]["frames_per_s"]
         result["speedup_vs_plain_referenced"] = fps / plain["referenced_views"]["frames_per_s"]
+
+    if not args.no_shapes:
+        result["paper_shapes"] = paper_shapes(args, torch, lfr, sync)
 
     if not args.no_batch:
         result["batched"] = batched(args, torch, lfr, sync)

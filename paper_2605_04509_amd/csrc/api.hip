@@ -25,7 +25,7 @@ enum Slot {
     kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
-    kNumSlots
+    kAliveSat, kNumSlots
 };
 
 struct Buf {
@@ -339,6 +339,7 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
 // Project every Gaussian for the clusters and views of `vt`, then sort each
 // cluster's Gaussians by depth (key = cluster << 32 | float32 depth bits).
 struct Projected {
+    int64_t Mp = 0;             // stride of the depth-sorted per-cluster segments
     GaussRec *rec = nullptr;
     ItemRec *items = nullptr;
     float2 *mean2d = nullptr;
@@ -374,25 +375,30 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
         return fail(ctx, LFR_ERR_UNSUPPORTED, "tile (%d bits) + cluster (%d bits) keys exceed 32 bits", tbits, cbits);
     if (MK > (int64_t)0xFFFFFFFFll)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "Gaussians x clusters = %lld exceeds 2^32", (long long)MK);
+    // depth keys: one segment of Mp >= M entries per cluster, padded to the
+    // sort's granule, so the depth sort is a segmented sort on 32 bits
+    const int64_t G = sort_segment_granule();
+    const int64_t Mp = (M + G - 1) / G * G, MKp = Mp * KC;
     ProjectOut po;
+    po.Mp = Mp;
     uint64_t *dkey1;
     uint32_t *dval1;
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
     CHK(ws_get_t(ctx, kItems, MK, &po.items));
-    CHK(ws_get_t(ctx, kDKey0, MK, &po.dkey));
-    CHK(ws_get_t(ctx, kDVal0, MK, &po.dval));
-    CHK(ws_get_t(ctx, kDKey1, MK, &dkey1));
-    CHK(ws_get_t(ctx, kDVal1, MK, &dval1));
+    CHK(ws_get_t(ctx, kDKey0, MKp, &po.dkey));
+    CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
+    CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
+    CHK(ws_get_t(ctx, kDVal1, MKp, &dval1));
     CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
-    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MK), &sort_temp));
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MKp), &sort_temp));
     const size_t e0 = tm.mark(s);
     const TileGrid tg{d->W, d->H, d->tw, d->th, dt.cv_off, dt.cv_list};
     HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, tg, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStProject, e0, e1);
     bool alt = false;
-    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MK, 0, 32 + cbits, sort_temp, &alt, s));
+    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, Mp));
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
     out->items = po.items;
@@ -401,15 +407,17 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     out->dvs = alt ? dval1 : po.dval;
     out->cbits = cbits;
     out->tbits = tbits;
+    out->Mp = Mp;
     return LFR_OK;
 }
 
-BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int cbits,
+BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int64_t Mp, int cbits,
                      const uint32_t *alive, const ItemRec *items)
 {
     const Grid *d = &d_;
     BinParams bp;
     bp.M = M;
+    bp.Mp = Mp;
     bp.n_clusters = vt.n_clusters;
     bp.W = d->W;
     bp.H = d->H;
@@ -424,6 +432,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive_words = (d->TX + 31) / 32;
     bp.items = items;
     bp.alive_total = nullptr;
+    bp.alive_sat = nullptr;
     return bp;
 }
 
@@ -484,7 +493,7 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     CHK(ws_get_t(ctx, kPairV0, P, &pv0));
     CHK(ws_get_t(ctx, kPairK1, P, &pk1));
     CHK(ws_get_t(ctx, kPairV1, P, &pv1));
-    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.M * bp.n_clusters))),
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.Mp * bp.n_clusters))),
                &sort_temp));
     HIPCHK(ctx, launch_chunk_emit(bp, pr.dks, pr.dvs, r0, len, offsets, P, pk0, pv0, s));
     const size_t e1 = tm.mark(s);
@@ -686,6 +695,8 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
     HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
     HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+    uint32_t *alive_sat;
+    CHK(ws_get_t(ctx, kAliveSat, (size_t)vt.n_clusters * (d->TY + 1) * (d->TX + 1) + 1, &alive_sat));
 
     BlendParams bp;
     bp.W = d->W;
@@ -718,7 +729,7 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
         CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
         CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
     }
-    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.cbits, alive_bits, pr.items);
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items);
     if (planned) bin.alive_total = &d_tot->alive;
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
@@ -764,6 +775,8 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
             ++ctx->stats.blend_launches;
             if (!last) {
                 HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+                HIPCHK(ctx, launch_alive_sat(tc_alive, vt.n_clusters, d->TX, d->TY, pr.cbits, alive_sat, s));
+                bin.alive_sat = alive_sat;   // later chunks skip items whose tiles are all saturated
                 tm.span(kStRanges, e1, tm.mark(s));
             }
             blend_ran = true;
@@ -1217,7 +1230,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
-        const BinParams bin = bin_params(fg, dt, vt, M, pr.cbits, alive_bits, pr.items);
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;

@@ -25,6 +25,17 @@ __device__ inline int item_units(const ItemRec &r)
     return ((int)r.bbox.w - (int)r.bbox.z + 1) * (((int)r.bbox.y >> 5) - ((int)r.bbox.x >> 5) + 1);
 }
 
+// Whether any (tile, cluster k) list inside the tile rectangle b (inclusive
+// x0, x1, y0, y1) still has unsaturated subpixels: four lookups in the
+// cluster's summed-area table of alive lists.
+__device__ inline bool rect_alive(const BinParams &bp, int k, ushort4 b)
+{
+    const int64_t pitch = bp.TX + 1;
+    const uint32_t *S = bp.alive_sat + (int64_t)k * (bp.TY + 1) * pitch;
+    const int64_t y0 = b.z, y1 = (int64_t)b.w + 1, x0 = b.x, x1 = (int64_t)b.y + 1;
+    return S[y1 * pitch + x1] - S[y0 * pitch + x1] - S[y1 * pitch + x0] + S[y0 * pitch + x0] != 0u;
+}
+
 // Tiles of the item in unit u: the OR of its views' boxes (or its bounding
 // box when it has more boxes than the record holds) in that row and word,
 // restricted to alive lists.  Also returns the unit's row and word.
@@ -120,10 +131,12 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     uint32_t i = 0;
     int U = 0;
     if (in) {
-        const int64_t e = (int64_t)k * bp.M + r0 + rl;
+        const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
         if ((uint32_t)dkey_sorted[e] != 0xFFFFFFFFu) {
             i = dval_sorted[e];
-            U = item_units(items_k[i]);
+            const ItemRec &it = items_k[i];
+            // items whose tiles are all saturated emit nothing: skip their units
+            if (!bp.alive_sat || (it.nv != 0 && rect_alive(bp, k, it.bbox))) U = item_units(it);
         }
     }
     const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);
@@ -223,6 +236,44 @@ __global__ void __launch_bounds__(256) alive_bits_kernel(const uint32_t *__restr
     bits[wid] = m;
 }
 
+// Summed-area table of alive (tile, cluster) lists, one block per cluster:
+// sat[k][y][x] = number of lists with tile row < y and tile column < x whose
+// unsaturated-subpixel count is non-zero.  Rows are prefixed by one wavefront
+// each (64 tiles per step), then columns by one thread each.
+__global__ void __launch_bounds__(256) alive_sat_kernel(const uint32_t *__restrict__ tc_alive, int TX, int TY,
+                                                         int cluster_bits, uint32_t *__restrict__ sat)
+{
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    const int64_t pitch = TX + 1;
+    uint32_t *S = sat + (int64_t)k * (TY + 1) * pitch;
+    for (int x = threadIdx.x; x <= TX; x += blockDim.x) S[x] = 0u;
+    for (int ty = wave; ty < TY; ty += n_waves) {
+        uint32_t *row = S + (int64_t)(ty + 1) * pitch;
+        if (lane == 0) row[0] = 0u;
+        uint32_t carry = 0;
+        for (int x0 = 0; x0 < TX; x0 += 64) {
+            const int tx = x0 + lane;
+            uint32_t v = 0;
+            if (tx < TX) {
+                const uint32_t t = (uint32_t)(ty * TX + tx);
+                v = tc_alive[(t << cluster_bits) | (uint32_t)k] > 0 ? 1u : 0u;
+            }
+            const uint32_t incl = wave_incl_scan(v, lane);
+            if (tx < TX) row[tx + 1] = carry + incl;
+            carry += (uint32_t)__shfl((int)incl, 63, 64);
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x <= TX; x += blockDim.x) {
+        uint32_t run = 0;
+        for (int y = 1; y <= TY; ++y) {
+            run += S[(int64_t)y * pitch + x];
+            S[(int64_t)y * pitch + x] = run;
+        }
+    }
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
@@ -274,6 +325,15 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStr
 hipError_t launch_record_count(const uint64_t *src, uint64_t *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(record_count_kernel, dim3(1), dim3(1), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int cluster_bits, uint32_t *sat,
+                            hipStream_t s)
+{
+    if (n_clusters == 0) return hipSuccess;
+    hipLaunchKernelGGL(alive_sat_kernel, dim3((unsigned)n_clusters), dim3(256), 0, s, tc_alive, TX, TY, cluster_bits,
+                       sat);
     return hipGetLastError();
 }
 

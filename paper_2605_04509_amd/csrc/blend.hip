@@ -198,13 +198,28 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
                 // groups of 4 steps with a constant-trip inner loop, so the
                 // steps unroll despite the wavefront votes inside them
                 for (int g4 = g0; g4 < g1; g4 += 4) {
+                    // the group's LDS reads are all issued before its first step
+                    float4 A[4];
+                    float2 MU[4];
+                    float CU[4], TH[4];
+#pragma unroll
+                    for (int gk = 0; gk < 4; ++gk) {
+                        A[gk] = s_a[g4 + gk];
+                        CU[gk] = s_c[(g4 + gk) * 4 + u];
+                        TH[gk] = s_c[(g4 + gk) * 4 + 3];
+                        MU[gk] = s_mu[my_run][g4 + gk];
+                    }
+                    // keep the opacity and colour reads here rather than sunk
+                    // into the (rarely taken) branches that use them
+#pragma unroll
+                    for (int gk = 0; gk < 4; ++gk) asm volatile("" : : "v"(A[gk].w), "v"(CU[gk]));
 #pragma unroll
                     for (int gk = 0; gk < 4; ++gk) {
                         const int g = g4 + gk;
-                        const float4 a = s_a[g];
-                        const float thr = s_c[g * 4 + 3];
+                        const float4 a = A[gk];
+                        const float thr = TH[gk];
                         StepEval st;
-                        const float E = step_exponent(a, s_mu[my_run][g], px, py, st);
+                        const float E = step_exponent(a, MU[gk], px, py, st);
                         if (kCount) {
                             n_eval += (T > 0.0f && g < nb) ? 1u : 0u;
                             n_steps += lane == 0 ? 1u : 0u;
@@ -221,7 +236,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
                             n_live += (lane == 0 && __ballot(pass & (T > 0.0f)) != 0) ? 1u : 0u;
                         }
                         const float Cb = C + T * bgu;
-                        C = take ? fmaf(s_c[g * 4 + u] * alpha, T, C) : (stop ? Cb : C);
+                        C = take ? fmaf(CU[gk] * alpha, T, C) : (stop ? Cb : C);
                         if (kSave) {
                             endp = take ? base + (uint32_t)g + 1u : endp;
                             Tsave = stop ? T : (take ? Tn : Tsave);

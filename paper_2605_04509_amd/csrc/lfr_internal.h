@@ -180,9 +180,10 @@ struct SceneDev {
 struct ProjectOut {
     GaussRec *rec;      // [K'][M]
     ItemRec *items;     // [K'][M]  tile boxes per cluster view
-    uint64_t *dkey;     // [K'][M]  (cluster << 32) | depth bits, 0xFFFFFFFF if invalid
-    uint32_t *dval;     // [K'][M]  Gaussian index
+    uint64_t *dkey;     // [K'][Mp] (cluster << 32) | depth bits, 0xFFFFFFFF if invalid or padding
+    uint32_t *dval;     // [K'][Mp] Gaussian index
     float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
+    int64_t Mp;         // M rounded up to the sort's segment granule
 };
 struct TileGrid {
     int W, H, tw, th;
@@ -209,11 +210,15 @@ size_t sort_temp_bytes(int64_t n);
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s,
                           Timer *tm = nullptr, const uint64_t *dn = nullptr);
+// seg_len > 0: a segmented sort of n / seg_len independent segments of
+// seg_len keys each (seg_len a multiple of sort_segment_granule()).
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
-                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s);
+                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s, int64_t seg_len = 0);
+int64_t sort_segment_granule();
 
 struct BinParams {
     int64_t M;
+    int64_t Mp;               // stride of the per-cluster depth-sorted arrays
     int n_clusters;
     int W, H, tw, th, TX, TY;
     int cluster_bits;
@@ -223,6 +228,7 @@ struct BinParams {
     int alive_words;          // 32-bit words per tile row
     const ItemRec *items;     // [K'][M]
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
+    const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
 };
 hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
                               int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
@@ -235,6 +241,8 @@ hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStre
                          const uint64_t *dP = nullptr);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
 hipError_t launch_record_count(const uint64_t *src, uint64_t *dst, hipStream_t s);
+hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int cluster_bits, uint32_t *sat,
+                            hipStream_t s);
 hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
                              int cluster_bits, uint32_t *bits, hipStream_t s);
 hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,

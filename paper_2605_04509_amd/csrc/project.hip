@@ -258,8 +258,16 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
 {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc.M) return;
-    const int64_t M = sc.M;
+    const int64_t M = sc.M, Mp = out.Mp;
+    if (i >= M) {
+        // padding of each cluster's depth-key segment: sorts last, never read
+        if (i < Mp)
+            for (int k = 0; k < n_clusters; ++k) {
+                out.dkey[(int64_t)k * Mp + i] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
+                out.dval[(int64_t)k * Mp + i] = 0u;
+            }
+        return;
+    }
     GaussIn g;
     float shc[NB * 3];
     load_gaussian<DEG>(sc, i, g, shc);
@@ -280,8 +288,8 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
         FullProj f;
         f.valid = false;
         if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
-        const int64_t idx = (int64_t)k * M + i;
-        out.dval[idx] = (uint32_t)i;
+        const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
+        out.dval[kidx] = (uint32_t)i;
         if (f.valid) {
             GaussRec r;
             r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
@@ -296,9 +304,10 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
             it.flags = 0;
             unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
             for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
-                const MeanProj mv = project_mean(cams[view_cam[tg.cv_list[v]]], mx, my, mz, g.finite);
+                // this thread wrote the view's mean above (NaN if invalid)
+                const float2 m2 = out.mean2d[(int64_t)tg.cv_list[v] * M + i];
                 ushort4 b;
-                if (!mv.valid || !tile_box(mv.m2d, f.ext, tg, b)) continue;
+                if (isnan(m2.x) || !tile_box(m2, f.ext, tg, b)) continue;
                 if (it.nv < kItemViews) it.r[it.nv++] = b;
                 else it.flags = 1;
                 x0 = min(x0, b.x);
@@ -309,9 +318,9 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
             it.bbox = make_ushort4(x0, x1, y0, y1);
             for (int q = it.nv; q < kItemViews; ++q) it.r[q] = make_ushort4(1, 0, 1, 0);
             out.items[idx] = it;
-            out.dkey[idx] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(m.depth);
+            out.dkey[kidx] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(m.depth);
         } else {
-            out.dkey[idx] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
+            out.dkey[kidx] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
         }
     }
 }
@@ -355,8 +364,9 @@ hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileG
                           const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
                           const ProjectOut &out, hipStream_t s)
 {
-    if (sc.M == 0) return hipSuccess;
-    const dim3 grid((unsigned)((sc.M + 255) / 256)), block(256);
+    const int64_t n = sc.M > out.Mp ? sc.M : out.Mp;
+    if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     switch (sc.deg) {
     case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
     case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;

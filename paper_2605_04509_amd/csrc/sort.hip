@@ -13,6 +13,16 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kSortWaves = kSortBlock / 64;
 
+// Histogram layout: [digit][tile] for one segment; with segments of seg
+// tiles each (seg > 0), [segment][digit][tile in segment], so that one
+// linear exclusive scan keeps every segment's keys inside the segment (a
+// segmented sort: keys never cross segment boundaries).
+__device__ __forceinline__ int64_t hist_index(int d, int64_t tile, int64_t nb, int64_t seg)
+{
+    if (seg == 0) return (int64_t)d * nb + tile;
+    return ((tile / seg) * 256 + d) * seg + tile % seg;
+}
+
 // The element count is n, or min(*dn, n) when dn is given (a count known only
 // on the device; the grid is sized for n).
 __device__ __forceinline__ int64_t sort_count(int64_t n, const uint64_t *dn)
@@ -25,7 +35,7 @@ __device__ __forceinline__ int64_t sort_count(int64_t n, const uint64_t *dn)
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restrict__ keys, int64_t n_cap,
                                                                 const uint64_t *dn, int shift, uint32_t mask,
-                                                                uint32_t *hist, int64_t nb)
+                                                                uint32_t *hist, int64_t nb, int64_t seg)
 {
     const int64_t n = sort_count(n_cap, dn);
     __shared__ uint32_t h[256];
@@ -38,7 +48,7 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
         if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    hist[hist_index(threadIdx.x, blockIdx.x, nb, seg)] = h[threadIdx.x];
 }
 
 // Scatter of one 4096-key tile.  Wavefront w ranks the contiguous keys
@@ -54,7 +64,8 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
                                                                    K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                    int64_t n_cap, const uint64_t *dn, int shift,
                                                                    uint32_t mask, const uint32_t *__restrict__ offs,
-                                                                   const uint32_t *__restrict__ hist, int64_t nb)
+                                                                   const uint32_t *__restrict__ hist, int64_t nb,
+                                                                   int64_t seg)
 {
     const int64_t n = sort_count(n_cap, dn);
     constexpr int kPerWave = kSortTile / kSortWaves;  // 1024
@@ -71,7 +82,8 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
 
     // digit starts inside the tile: exclusive scan of this tile's histogram
     {
-        const uint32_t h = hist[(int64_t)tid * nb + blockIdx.x];
+        const int64_t hi = hist_index(tid, blockIdx.x, nb, seg);
+        const uint32_t h = hist[hi];
         uint32_t incl = h;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -79,7 +91,7 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
             if (lane >= d) incl += t;
         }
         if (lane == 63) s_wsum[wave] = incl;
-        s_gbase[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+        s_gbase[tid] = offs[hi];
 #pragma unroll
         for (int w = 0; w < kSortWaves; ++w) s_cnt[w][tid] = 0;
         __syncthreads();
@@ -157,7 +169,7 @@ size_t sort_temp_bytes(int64_t n)
 template <typename K>
 static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int b0, int b1,
                                   void *temp, bool *in_alt, hipStream_t s, Timer *tm = nullptr,
-                                  const uint64_t *dn = nullptr)
+                                  const uint64_t *dn = nullptr, int64_t seg = 0)
 {
     *in_alt = false;
     if (n <= 1 || b1 <= b0) return hipSuccess;
@@ -172,12 +184,12 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
         const int bits = (b1 - shift) < 8 ? (b1 - shift) : 8;
         const uint32_t mask = (1u << bits) - 1u;
         hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, n, dn, shift,
-                           mask, hist, nb);
+                           mask, hist, nb, seg);
         hipError_t e = launch_exclusive_scan(hist, offs, nh, stemp, nullptr, s);
         if (e != hipSuccess) return e;
         const size_t ea = tm ? tm->mark(s) : 0;
         hipLaunchKernelGGL(sort_scatter_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, vi, ko, vo, n,
-                           dn, shift, mask, offs, hist, nb);
+                           dn, shift, mask, offs, hist, nb, seg);
         if (tm) tm->span(kStScatter, ea, tm->mark(s));
         K *tk = ki;
         ki = ko;
@@ -197,9 +209,13 @@ hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s)
+                          void *temp, bool *in_alt, hipStream_t s, int64_t seg_len)
 {
-    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s);
+    if (seg_len > 0 && (seg_len % kSortTile != 0 || n % seg_len != 0)) return hipErrorInvalidValue;
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, nullptr, nullptr,
+                                     seg_len > 0 ? seg_len / kSortTile : 0);
 }
+
+int64_t sort_segment_granule() { return kSortTile; }
 
 }  // namespace lfr

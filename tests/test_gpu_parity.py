@@ -412,3 +412,39 @@ def test_outdoor_workload_bench_configuration(lib):
     say(info)
     assert np.isfinite(img).all()
     d.close()
+
+
+@pytest.mark.parametrize("name,S,views", [("landscape71", 18, [19, 27]), ("portrait63", 16, [33, 40])])
+def test_paper_display_shapes(lib, name, S, views):
+    """The paper's two display shapes (71 views over 53 degrees at 3840x2160
+    with reuse groups of 18; 63 views over 53 degrees at 1440x2560 with groups
+    of 16, the last group padded) on the 3M-Gaussian scene: sampled subpixels
+    of two views of one cluster against the oracle, and the exact path's
+    image against full-frame-then-interlace on the same display."""
+    lfr, ctx = lib
+    w = get_workload(name)
+    say(name, "S =", S, "views", views)
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    V = oracle.view_map(w.display)
+    assert len(np.unique(V)) == w.display.num_views
+    params = w.display.with_tile(32, 32)
+    d = _display(lfr, ctx, params)
+    ds = lfr.DeviceScene.from_numpy(scene)
+    img = _render(lfr, ctx, d, ds, cams, cluster_size=S)
+    samples = _sample_in_views(V, views, 100, 3)
+    ref, flags, tflag = oracle.render_subpixels(scene, cams, params, V, S, samples)
+    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
+                   label=f"{name} S={S}")
+    say(info)
+    # the last cluster is padded with the last view: its subpixels too
+    last = [w.display.num_views - 1]
+    samples = _sample_in_views(V, last, 60, 3)
+    ref, flags, tflag = oracle.render_subpixels(scene, cams, params, V, S, samples)
+    compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
+            label=f"{name} S={S} padded cluster")
+    exact = _render(lfr, ctx, d, ds, cams, cluster_size=1)
+    ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=18, tile=32)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ff.cpu().numpy(), exact)
+    d.close()

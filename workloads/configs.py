@@ -6,14 +6,21 @@
                slant 1/6, pitch 5.
 * ``outdoor``  3,000,000 Gaussians (clustered + far shell, SH3), 100 views
                over 50 degrees, 3840x2160, slant 1/5, pitch 31/5.
+* ``landscape71`` the outdoor scene on the paper's landscape shape: 71 views
+               over 53 degrees, 3840x2160, slant 3/17, pitch 123/20 (every view
+               owns subpixels; reuse groups of 18 views).
+* ``portrait63``   the outdoor scene on the paper's portrait shape: 63 views over
+               53 degrees, 1440x2560, slant 3/17, pitch 57/10 (every view owns
+               subpixels; reuse groups of 16 views).
 * ``batched``  three outdoor-style scenes (0.5M / 1M / 3M) on 1080p/45-view,
                1440p/64-view and 4K/100-view panels, 16 jittered head poses
                each.
 * ``grad``     the ``display`` workload for the differentiable path, plus a
                500-Gaussian 64x36 subset for finite-difference checks.
 
-Orbit geometry (radius, centre) and the c3/c4 scene details are this
-project's choices; the paper does not give them.
+Orbit geometry (radius, centre), the scene details and the lens slant /
+pitch of the two paper display shapes are this project's choices; the paper
+gives only view counts, angular ranges, resolutions and reuse group sizes.
 """
 from __future__ import annotations
 
@@ -62,6 +69,10 @@ WORKLOADS = {
                         _display, radius=6.0, span_deg=40.0, cluster_sizes=(1, 8)),
     "outdoor": Workload("outdoor", DisplayParams(3840, 2160, 100, Rational(1, 5), Rational(31, 5)),
                         _outdoor, radius=12.0, span_deg=50.0, cluster_sizes=(1, 2, 4, 8)),
+    "landscape71": Workload("landscape71", DisplayParams(3840, 2160, 71, Rational(3, 17), Rational(123, 20)),
+                            _outdoor, radius=12.0, span_deg=53.0, cluster_sizes=(1, 18)),
+    "portrait63": Workload("portrait63", DisplayParams(1440, 2560, 63, Rational(3, 17), Rational(57, 10)),
+                           _outdoor, radius=12.0, span_deg=53.0, cluster_sizes=(1, 16)),
 }
 
 
