@@ -337,13 +337,14 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
 }
 
 // Project every Gaussian for the clusters and views of `vt`, then sort each
-// cluster's Gaussians by depth (key = cluster << 32 | float32 depth bits).
+// cluster's Gaussians by depth (key = float32 depth bits, one sort segment
+// per cluster).
 struct Projected {
     int64_t Mp = 0;             // stride of the depth-sorted per-cluster segments
     GaussRec *rec = nullptr;
     ItemRec *items = nullptr;
     float2 *mean2d = nullptr;
-    const uint64_t *dks = nullptr;
+    const uint32_t *dks = nullptr;
     const uint32_t *dvs = nullptr;
     int cbits = 0, tbits = 0;
 };
@@ -381,7 +382,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     const int64_t Mp = (M + G - 1) / G * G, MKp = Mp * KC;
     ProjectOut po;
     po.Mp = Mp;
-    uint64_t *dkey1;
+    uint32_t *dkey1;
     uint32_t *dval1;
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
@@ -398,7 +399,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     const size_t e1 = tm.mark(s);
     tm.span(kStProject, e0, e1);
     bool alt = false;
-    HIPCHK(ctx, radix_sort_u64(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, Mp));
+    HIPCHK(ctx, radix_sort_u32(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, nullptr, nullptr, Mp));
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
     out->items = po.items;

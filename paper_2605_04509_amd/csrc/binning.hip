@@ -99,7 +99,7 @@ __device__ inline int wave_search(uint32_t key, uint32_t x)
 }
 
 // Items of one chunk: depth ranks [r0, r0 + len) of every cluster; item
-// (k, r) sits at k * M + r of the depth-sorted arrays and at k * len + (r - r0)
+// (k, r) sits at k * Mp + r of the depth-sorted arrays and at k * len + (r - r0)
 // of the chunk's count / offset arrays.
 //
 // Load balancing: each wavefront enumerates the units of its 64 consecutive
@@ -109,7 +109,7 @@ __device__ inline int wave_search(uint32_t key, uint32_t x)
 // wavefront's pairs out contiguously (its items' offsets are consecutive)
 // and writes them with consecutive lanes on consecutive slots.
 template <bool kEmit>
-__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const uint64_t *__restrict__ dkey_sorted,
+__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const uint32_t *__restrict__ dkey_sorted,
                                                            const uint32_t *__restrict__ dval_sorted, int64_t r0,
                                                            int64_t len, uint32_t *__restrict__ counts,
                                                            const uint32_t *__restrict__ offsets, uint64_t n_pairs,
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     int U = 0;
     if (in) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
-        if ((uint32_t)dkey_sorted[e] != 0xFFFFFFFFu) {
+        if (dkey_sorted[e] != 0xFFFFFFFFu) {
             i = dval_sorted[e];
             const ItemRec &it = items_k[i];
             // items whose tiles are all saturated emit nothing: skip their units
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(256) alive_sat_kernel(const uint32_t *__restri
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
                               int64_t r0, int64_t len, uint32_t *counts, hipStream_t s)
 {
     if (len == 0 || bp.n_clusters == 0) return hipSuccess;
@@ -286,7 +286,7 @@ hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, 
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_emit(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
                              int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs, uint32_t *pair_keys,
                              uint32_t *pair_vals, hipStream_t s)
 {

@@ -110,13 +110,15 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 // kSave (single-chunk renders) also writes each subpixel's final T (before
 // the fold) and the end of its blended list for the backward.
 template <bool kCount, bool kSave>
-__global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
                                                           int n_tasks, int per)
 {
     __shared__ float4 s_a[kWave];
     __shared__ float s_c[kWave * 4];
     __shared__ float2 s_mu[kMaxWaveViews][kWave];
     __shared__ int s_slot[kMaxWaveViews];
+    __shared__ float4 s_box[kMaxWaveViews];         // per view run: unfinished lanes' x0, x1, y0, y1
+    __shared__ uint32_t s_pos[kSave ? kWave : 1];    // list position of each staged entry
 
     const int ti = xcd_task(blockIdx.x, per);
     if (ti >= n_tasks) return;
@@ -156,6 +158,23 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
     float Tsave = T;
     unsigned long long n_eval = 0, n_blend = 0, n_steps = 0, n_live = 0;
     uint32_t endp = 0;
+    // sample-centre bounding box of each view run's unfinished lanes
+    if (!kCount) {
+#pragma unroll
+        for (int q = 0; q < kMaxWaveViews; ++q) {
+            if (q >= n_runs) break;
+            const bool in = (T > 0.0f) & (my_run == q);
+            float x0 = in ? px : 3e38f, x1 = in ? px : -3e38f, y0 = in ? py : 3e38f, y1 = in ? py : -3e38f;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                x0 = fminf(x0, __shfl_xor(x0, d, 64));
+                x1 = fmaxf(x1, __shfl_xor(x1, d, 64));
+                y0 = fminf(y0, __shfl_xor(y0, d, 64));
+                y1 = fmaxf(y1, __shfl_xor(y1, d, 64));
+            }
+            if (lane == 0) s_box[q] = make_float4(x0, x1, y0, y1);
+        }
+    }
     __syncthreads();
     int slots[kMaxWaveViews];
 #pragma unroll
@@ -181,17 +200,55 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
         }
         gc.w = cutoff_exponent(ga.w);
     };
+    // Whether this lane's fetched Gaussian can reach any unfinished lane: the
+    // region E <= E_cut lies in |dy| <= sqrt(E_cut / G'), |dx| <= sqrt(E_cut /
+    // A') + |beta| |dy| (E = A'(dx + beta dy)^2 + G' dy^2), widened by 0.1%
+    // and 1e-3 px for rounding; outside it alpha < 0.9986 / 255 for every lane,
+    // so dropping the Gaussian changes nothing.  The counting variant keeps
+    // every entry (its counts are the method's full work).
+    auto relevant = [&](uint32_t base) -> bool {
+        if (base + (uint32_t)lane >= range.y) return false;
+        if (kCount) return true;
+        const float thr = gc.w;
+        if (!(thr >= 0.0f)) return false;
+        const float hy = sqrtf(thr / ga.z) * 1.001f + 1e-3f;
+        const float hx = sqrtf(thr / ga.x) * 1.001f + fabsf(ga.y) * hy + 1e-3f;
+        bool r = false;
+#pragma unroll
+        for (int q = 0; q < kMaxWaveViews; ++q) {
+            if (q >= n_runs) break;
+            const float4 b = s_box[q];
+            r = r | ((gm[q].x + hx >= b.x) & (gm[q].x - hx <= b.y) & (gm[q].y + hy >= b.z) & (gm[q].y - hy <= b.w));
+        }
+        return r;
+    };
     if (__ballot(T > 0.0f) != 0 && range.x < range.y) {
         fetch(range.x);
         for (uint32_t base = range.x; base < range.y; base += kWave) {
-            s_a[lane] = ga;
-            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = gc;
+            // stage the relevant entries of this batch, compacted in list order
+            const bool rel = relevant(base);
+            const uint64_t rmask = __ballot(rel);
+            const int nb = __popcll(rmask);
+            if (rel) {
+                const int pos = __popcll(rmask & ((1ull << lane) - 1ull));
+                s_a[pos] = ga;
+                *reinterpret_cast<float4 *>(&s_c[pos * 4]) = gc;
 #pragma unroll
-            for (int q = 0; q < kMaxWaveViews; ++q)
-                if (q < n_runs) s_mu[q][lane] = gm[q];
+                for (int q = 0; q < kMaxWaveViews; ++q)
+                    if (q < n_runs) s_mu[q][pos] = gm[q];
+                if (kSave) s_pos[pos] = base + (uint32_t)lane;
+            }
+            if (lane >= nb && lane < ((nb + 3) & ~3)) {
+                // padding up to a multiple of 4 (slots no relevant entry uses,
+                // whatever this lane's own entry was): zero opacity, never passes
+                s_a[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_c[lane * 4 + 3] = -__builtin_inff();
+#pragma unroll
+                for (int q = 0; q < kMaxWaveViews; ++q)
+                    if (q < n_runs) s_mu[q][lane] = make_float2(0.f, 0.f);
+            }
             __syncthreads();
             if (base + kWave < range.y) fetch(base + kWave);
-            const int nb = (int)min((uint32_t)kWave, range.y - base);
             const int nb4 = (nb + 3) & ~3;
             for (int g0 = 0; g0 < nb4; g0 += 16) {
                 const int g1 = min(g0 + 16, nb4);
@@ -209,24 +266,37 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
                         TH[gk] = s_c[(g4 + gk) * 4 + 3];
                         MU[gk] = s_mu[my_run][g4 + gk];
                     }
-                    // keep the opacity and colour reads here rather than sunk
-                    // into the (rarely taken) branches that use them
+                    // the four exponents are independent: compute them together,
+                    // and skip the whole group when no unfinished lane is within
+                    // any of the four cutoffs
+                    StepEval st[4];
+                    float E[4];
 #pragma unroll
-                    for (int gk = 0; gk < 4; ++gk) asm volatile("" : : "v"(A[gk].w), "v"(CU[gk]));
+                    for (int gk = 0; gk < 4; ++gk) E[gk] = step_exponent(A[gk], MU[gk], px, py, st[gk]);
+                    // lane masks of "within the cutoff", combined on the scalar unit
+                    uint64_t within[4];
+#pragma unroll
+                    for (int gk = 0; gk < 4; ++gk) within[gk] = __ballot(E[gk] <= TH[gk]);
+                    const bool skip_group =
+                        ((within[0] | within[1] | within[2] | within[3]) & __ballot(T > 0.0f)) == 0;
+                    if (kCount && skip_group) {
+#pragma unroll
+                        for (int gk = 0; gk < 4; ++gk) {
+                            n_eval += (T > 0.0f && g4 + gk < nb) ? 1u : 0u;
+                            n_steps += lane == 0 ? 1u : 0u;
+                        }
+                    }
+                    if (skip_group) continue;
 #pragma unroll
                     for (int gk = 0; gk < 4; ++gk) {
                         const int g = g4 + gk;
-                        const float4 a = A[gk];
-                        const float thr = TH[gk];
-                        StepEval st;
-                        const float E = step_exponent(a, MU[gk], px, py, st);
                         if (kCount) {
                             n_eval += (T > 0.0f && g < nb) ? 1u : 0u;
                             n_steps += lane == 0 ? 1u : 0u;
                         }
-                        // no unfinished lane within the cutoff: nothing changes
-                        if (__ballot((T > 0.0f) & (E <= thr)) == 0) continue;
-                        const float alpha = step_alpha_of(a.w, E, st);
+                        // no unfinished lane within this cutoff: nothing changes
+                        if ((within[gk] & __ballot(T > 0.0f)) == 0) continue;
+                        const float alpha = step_alpha_of(A[gk].w, E[gk], st[gk]);
                         const float Tn = T * (1.0f - alpha);
                         const bool pass = alpha >= kAlphaMin;
                         const bool take = pass & (Tn >= kTStop);
@@ -238,7 +308,7 @@ __global__ void __launch_bounds__(64) blend_remap_kernel(BlendParams bp, const T
                         const float Cb = C + T * bgu;
                         C = take ? fmaf(CU[gk] * alpha, T, C) : (stop ? Cb : C);
                         if (kSave) {
-                            endp = take ? base + (uint32_t)g + 1u : endp;
+                            endp = take ? s_pos[g] + 1u : endp;
                             Tsave = stop ? T : (take ? Tn : Tsave);
                         }
                         T = take ? Tn : (stop ? 0.0f : T);

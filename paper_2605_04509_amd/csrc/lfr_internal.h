@@ -24,7 +24,7 @@ constexpr double kDilation = 0.3;           // 2D covariance dilation
 constexpr double kClampFov = 1.3;           // Jacobian clamp (x tan(fov/2))
 constexpr double kHalfLog2e = 0.5 * 1.44269504088896340736;
 constexpr int kMaxClusterViews = 32;        // views unioned per cluster
-constexpr int kMaxWaveViews = 8;            // distinct views in one blend wavefront
+constexpr int kMaxWaveViews = 4;            // distinct views in one blend wavefront
 constexpr int kWave = 64;
 
 // Camera in double precision, with the derived clamp limits and centre.
@@ -180,7 +180,7 @@ struct SceneDev {
 struct ProjectOut {
     GaussRec *rec;      // [K'][M]
     ItemRec *items;     // [K'][M]  tile boxes per cluster view
-    uint64_t *dkey;     // [K'][Mp] (cluster << 32) | depth bits, 0xFFFFFFFF if invalid or padding
+    uint32_t *dkey;     // [K'][Mp] float32 depth bits, 0xFFFFFFFF if invalid or padding
     uint32_t *dval;     // [K'][Mp] Gaussian index
     float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
     int64_t Mp;         // M rounded up to the sort's segment granule
@@ -207,9 +207,11 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, v
 size_t sort_temp_bytes(int64_t n);
 // With a timer, every scatter launch is recorded as a kStScatter span.  With
 // dn, the count is min(*dn, n) read on the device (n sizes the grid and temp).
+// seg_len > 0: a segmented sort of n / seg_len independent segments of
+// seg_len keys each (seg_len a multiple of sort_segment_granule()).
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                           int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s,
-                          Timer *tm = nullptr, const uint64_t *dn = nullptr);
+                          Timer *tm = nullptr, const uint64_t *dn = nullptr, int64_t seg_len = 0);
 // seg_len > 0: a segmented sort of n / seg_len independent segments of
 // seg_len keys each (seg_len a multiple of sort_segment_granule()).
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
@@ -230,9 +232,9 @@ struct BinParams {
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
 };
-hipError_t launch_chunk_count(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
                               int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
-hipError_t launch_chunk_emit(const BinParams &bp, const uint64_t *dkey_sorted, const uint32_t *dval_sorted,
+hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
                              int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs,
                              uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

@@ -251,7 +251,7 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
                                                       int n_clusters, const int32_t *__restrict__ cluster_cam,
                                                       int n_views, const int32_t *__restrict__ view_cam,
                                                       ProjectOut out)
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
         // padding of each cluster's depth-key segment: sorts last, never read
         if (i < Mp)
             for (int k = 0; k < n_clusters; ++k) {
-                out.dkey[(int64_t)k * Mp + i] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
+                out.dkey[(int64_t)k * Mp + i] = 0xFFFFFFFFu;
                 out.dval[(int64_t)k * Mp + i] = 0u;
             }
         return;
@@ -287,7 +287,9 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
         const MeanProj m = project_mean(c, mx, my, mz, g.finite);
         FullProj f;
         f.valid = false;
-        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
+        // the SH coefficients are read again from the scene (cache hits) rather
+        // than held in registers across the loop: fewer registers, more waves
+        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, sc.sh + (int64_t)NB * 3 * i);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
         if (f.valid) {
@@ -318,9 +320,9 @@ __global__ void __launch_bounds__(256) project_kernel(SceneDev sc, const DevCame
             it.bbox = make_ushort4(x0, x1, y0, y1);
             for (int q = it.nv; q < kItemViews; ++q) it.r[q] = make_ushort4(1, 0, 1, 0);
             out.items[idx] = it;
-            out.dkey[kidx] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(m.depth);
+            out.dkey[kidx] = __float_as_uint(m.depth);
         } else {
-            out.dkey[kidx] = ((uint64_t)k << 32) | 0xFFFFFFFFull;
+            out.dkey[kidx] = 0xFFFFFFFFu;
         }
     }
 }

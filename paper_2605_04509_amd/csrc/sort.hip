@@ -203,9 +203,11 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
 }
 
 hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s, Timer *tm, const uint64_t *dn)
+                          void *temp, bool *in_alt, hipStream_t s, Timer *tm, const uint64_t *dn, int64_t seg_len)
 {
-    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm, dn);
+    if (seg_len > 0 && (seg_len % kSortTile != 0 || n % seg_len != 0)) return hipErrorInvalidValue;
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm, dn,
+                                     seg_len > 0 ? seg_len / kSortTile : 0);
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
