@@ -551,9 +551,14 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
     HIPCHK(ctx, hipMemcpyAsync(&n, tot, sizeof n, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     HIPCHK(ctx, hipMalloc(&ts.d_tasks, sizeof(Task) * std::max<uint64_t>(n, 1)));
-    HIPCHK(ctx, launch_task_emit(d->d_V, d->d_psi, ts.d_view_cluster, d->W, d->H, d->tw, d->th, off, ts.d_tasks, s));
+    int32_t *vslot = nullptr;
+    HIPCHK(ctx, hipMalloc(&vslot, sizeof(int32_t) * d->N));
+    HIPCHK(ctx, hipMemcpy(vslot, vt.view_slot.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice));
+    HIPCHK(ctx, launch_task_emit(d->d_V, d->d_psi, ts.d_view_cluster, vslot, d->W, d->H, d->tw, d->th, off,
+                                 ts.d_tasks, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ts.n = (int)n;
+    (void)hipFree(vslot);
     (void)hipFree(cnt);
     (void)hipFree(off);
     (void)hipFree(tot);

@@ -68,10 +68,24 @@ __device__ __forceinline__ float2 sanitize_mean(float2 m)
     return isnan(m.x) ? make_float2(kFarMean, kFarMean) : m;
 }
 
-// Block index -> task index such that each of the 8 XCDs (which receive
-// blocks round-robin) works on one contiguous range of tasks; neighbouring
-// tiles then share their XCD's L2.  The grid has 8 * per blocks.
-__device__ __forceinline__ int xcd_task(int b, int per) { return (b & 7) * per + (b >> 3); }
+// Block index -> task index.  Blocks are dealt to the 8 XCDs round-robin;
+// XCD x runs task groups x, x + 8, x + 16, ... (groups of kXcdGroup
+// consecutive tasks) in order.  The tasks of one (tile, cluster) list are
+// consecutive, so they mostly share one XCD and its L2, while every XCD
+// sweeps the whole panel: the work per tile varies strongly across the
+// panel, and contiguous eighths of it would leave some XCDs idle early.
+// The grid is rounded up to whole rounds of 8 groups.
+constexpr int kXcdGroup = 16;
+__device__ __forceinline__ int xcd_task(int b)
+{
+    const int x = b & 7, l = b >> 3;
+    return ((l / kXcdGroup) * 8 + x) * kXcdGroup + (l % kXcdGroup);
+}
+static unsigned xcd_grid(int n_tasks)
+{
+    const int r = 8 * kXcdGroup;
+    return (unsigned)((n_tasks + r - 1) / r * r);
+}
 
 // Sum of a per-lane count over the wavefront, added once to a counter.
 __device__ __forceinline__ void add_work(unsigned long long *dst, unsigned long long v)
@@ -110,17 +124,16 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 // kSave (single-chunk renders) also writes each subpixel's final T (before
 // the fold) and the end of its blended list for the backward.
 template <bool kCount, bool kSave>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
-                                                          int n_tasks, int per)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
+                                                          int n_tasks)
 {
     __shared__ float4 s_a[kWave];
     __shared__ float s_c[kWave * 4];
     __shared__ float2 s_mu[kMaxWaveViews][kWave];
-    __shared__ int s_slot[kMaxWaveViews];
     __shared__ float4 s_box[kMaxWaveViews];         // per view run: unfinished lanes' x0, x1, y0, y1
-    __shared__ uint32_t s_pos[kSave ? kWave : 1];    // list position of each staged entry
+    __shared__ uint32_t s_pos[kSave || kCount ? kWave : 1];  // list position of each staged entry
 
-    const int ti = xcd_task(blockIdx.x, per);
+    const int ti = xcd_task(blockIdx.x);
     if (ti >= n_tasks) return;
     if (!bp.first && !bp.task_alive[ti]) return;
     const Task tk = tasks[ti];
@@ -128,21 +141,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
     const bool active = lane < (int)tk.count;
     const uint32_t at = tk.start + (active ? lane : (int)tk.count - 1);
     const uint32_t p = bp.psi[at];
-    const int j = bp.V[p];
     const uint32_t pix = p / 3;
     const int u = (int)(p - 3 * pix);
     const uint32_t y = pix / (uint32_t)bp.W;
     const uint32_t x = pix - y * (uint32_t)bp.W;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const float bgu = bp.bg[u];
-
-    // distinct views of this wavefront (Psi is sorted by view inside a tile)
-    const int jprev = __shfl_up(j, 1, 64);
-    const bool first = lane == 0 || j != jprev;
-    const uint64_t runs = __ballot(first);
-    const int my_run = __popcll(runs & ((2ull << lane) - 1ull)) - 1;
-    const int n_runs = __popcll(runs);
-    if (first) s_slot[my_run] = bp.view_slot[j];
+    // this lane's view run (the task's lanes are runs of one view each)
+    const int n_runs = tk.n_runs;
+    const int my_run = (lane >= (int)tk.run_start[1]) + (lane >= (int)tk.run_start[2]) + (lane >= (int)tk.run_start[3]);
 
     const uint32_t list = (tk.tile << bp.cluster_bits) | tk.cluster;
     const uint2 range = bp.ranges[list];
@@ -156,10 +163,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
     if (!active) T = 0.0f;
     const bool was_done = T == 0.0f;
     float Tsave = T;
-    unsigned long long n_eval = 0, n_blend = 0, n_steps = 0, n_live = 0;
+    unsigned long long n_blend = 0, n_steps = 0, n_live = 0;
     uint32_t endp = 0;
+    uint32_t stopl = range.y;  // (counting) list position after this lane's stop
     // sample-centre bounding box of each view run's unfinished lanes
-    if (!kCount) {
+    {
 #pragma unroll
         for (int q = 0; q < kMaxWaveViews; ++q) {
             if (q >= n_runs) break;
@@ -178,11 +186,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
     __syncthreads();
     int slots[kMaxWaveViews];
 #pragma unroll
-    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = q < n_runs ? s_slot[q] : 0;
+    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = tk.slot[q];
 
-    // registers holding the batch being fetched
+    // Registers holding the batch being fetched, and the Gaussian indices of
+    // the batch after it.  fetch() only issues loads (the record and means of
+    // batch `base`, whose indices arrived during the previous batch, and the
+    // indices of the next one); their values are first used when the batch
+    // is staged, after the walk of the batch before it.
     float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gc = ga;
     float2 gm[kMaxWaveViews];
+    uint32_t nidx = 0;
+    auto load_index = [&](uint32_t base) {
+        const uint32_t e = base + (uint32_t)lane;
+        nidx = e < range.y ? bp.vals[e] : 0u;
+    };
     auto fetch = [&](uint32_t base) {
         const uint32_t e = base + (uint32_t)lane;
         ga = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -190,25 +207,26 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
 #pragma unroll
         for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = make_float2(0.f, 0.f);
         if (e < range.y) {
-            const uint32_t i = bp.vals[e];
+            const uint32_t i = nidx;
             const GaussRec g = rec[i];
             ga = g.a;
             gc = g.c;
 #pragma unroll
             for (int q = 0; q < kMaxWaveViews; ++q)
-                if (q < n_runs) gm[q] = sanitize_mean(bp.mean2d[(int64_t)slots[q] * bp.M + i]);
+                if (q < n_runs) gm[q] = bp.mean2d[(int64_t)slots[q] * bp.M + i];
         }
-        gc.w = cutoff_exponent(ga.w);
+        load_index(base + kWave);
     };
     // Whether this lane's fetched Gaussian can reach any unfinished lane: the
     // region E <= E_cut lies in |dy| <= sqrt(E_cut / G'), |dx| <= sqrt(E_cut /
     // A') + |beta| |dy| (E = A'(dx + beta dy)^2 + G' dy^2), widened by 0.1%
     // and 1e-3 px for rounding; outside it alpha < 0.9986 / 255 for every lane,
-    // so dropping the Gaussian changes nothing.  The counting variant keeps
-    // every entry (its counts are the method's full work).
+    // so dropping the Gaussian changes nothing.
     auto relevant = [&](uint32_t base) -> bool {
+        gc.w = cutoff_exponent(ga.w);
+#pragma unroll
+        for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = sanitize_mean(gm[q]);
         if (base + (uint32_t)lane >= range.y) return false;
-        if (kCount) return true;
         const float thr = gc.w;
         if (!(thr >= 0.0f)) return false;
         const float hy = sqrtf(thr / ga.z) * 1.001f + 1e-3f;
@@ -223,6 +241,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
         return r;
     };
     if (__ballot(T > 0.0f) != 0 && range.x < range.y) {
+        load_index(range.x);
         fetch(range.x);
         for (uint32_t base = range.x; base < range.y; base += kWave) {
             // stage the relevant entries of this batch, compacted in list order
@@ -236,7 +255,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
 #pragma unroll
                 for (int q = 0; q < kMaxWaveViews; ++q)
                     if (q < n_runs) s_mu[q][pos] = gm[q];
-                if (kSave) s_pos[pos] = base + (uint32_t)lane;
+                if (kSave || kCount) s_pos[pos] = base + (uint32_t)lane;
             }
             if (lane >= nb && lane < ((nb + 3) & ~3)) {
                 // padding up to a multiple of 4 (slots no relevant entry uses,
@@ -279,21 +298,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
                     for (int gk = 0; gk < 4; ++gk) within[gk] = __ballot(E[gk] <= TH[gk]);
                     const bool skip_group =
                         ((within[0] | within[1] | within[2] | within[3]) & __ballot(T > 0.0f)) == 0;
-                    if (kCount && skip_group) {
-#pragma unroll
-                        for (int gk = 0; gk < 4; ++gk) {
-                            n_eval += (T > 0.0f && g4 + gk < nb) ? 1u : 0u;
-                            n_steps += lane == 0 ? 1u : 0u;
-                        }
-                    }
+                    if (kCount) n_steps += lane == 0 ? (unsigned)min(4, nb - g4) : 0u;
                     if (skip_group) continue;
 #pragma unroll
                     for (int gk = 0; gk < 4; ++gk) {
                         const int g = g4 + gk;
-                        if (kCount) {
-                            n_eval += (T > 0.0f && g < nb) ? 1u : 0u;
-                            n_steps += lane == 0 ? 1u : 0u;
-                        }
                         // no unfinished lane within this cutoff: nothing changes
                         if ((within[gk] & __ballot(T > 0.0f)) == 0) continue;
                         const float alpha = step_alpha_of(A[gk].w, E[gk], st[gk]);
@@ -304,6 +313,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
                         if (kCount) {
                             n_blend += take ? 1u : 0u;
                             n_live += (lane == 0 && __ballot(pass & (T > 0.0f)) != 0) ? 1u : 0u;
+                            stopl = stop ? s_pos[g] + 1u : stopl;
                         }
                         const float Cb = C + T * bgu;
                         C = take ? fmaf(CU[gk] * alpha, T, C) : (stop ? Cb : C);
@@ -343,7 +353,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) bl
         }
     }
     if (kCount) {
-        add_work(bp.work, n_eval);
+        // the method evaluates every list entry up to and including the one
+        // at which the lane stops (culled entries included)
+        add_work(bp.work, was_done ? 0ull : (unsigned long long)(stopl - range.x));
         add_work(bp.work + 1, n_blend);
         add_work(bp.work + 2, n_steps);
         add_work(bp.work + 3, n_live);
@@ -533,34 +545,27 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const Task *__restrict__ tasks,
-                                                             int n_tasks, int per)
+                                                             int n_tasks)
 {
     __shared__ float4 s_a[kWave];
     __shared__ float s_c[kWave * 4];
     __shared__ float2 s_mu[kMaxWaveViews][kWave];
     __shared__ uint32_t s_i[kWave];
-    __shared__ int s_slot[kMaxWaveViews];
 
-    const int ti = xcd_task(blockIdx.x, per);
+    const int ti = xcd_task(blockIdx.x);
     if (ti >= n_tasks) return;
     const Task tk = tasks[ti];
     const int lane = threadIdx.x;
     const bool active = lane < (int)tk.count;
     const uint32_t at = tk.start + (active ? lane : (int)tk.count - 1);
     const uint32_t p = bp.psi[at];
-    const int j = bp.V[p];
     const uint32_t pix = p / 3;
     const int u = (int)(p - 3 * pix);
     const uint32_t y = pix / (uint32_t)bp.W;
     const uint32_t x = pix - y * (uint32_t)bp.W;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-
-    const int jprev = __shfl_up(j, 1, 64);
-    const bool first = lane == 0 || j != jprev;
-    const uint64_t runs = __ballot(first);
-    const int my_run = __popcll(runs & ((2ull << lane) - 1ull)) - 1;
-    const int n_runs = __popcll(runs);
-    if (first) s_slot[my_run] = bp.view_slot[j];
+    const int n_runs = tk.n_runs;
+    const int my_run = (lane >= (int)tk.run_start[1]) + (lane >= (int)tk.run_start[2]) + (lane >= (int)tk.run_start[3]);
 
     const float gout = active ? bp.grad_out[p] : 0.0f;
     const uint32_t end = (active && gout != 0.0f) ? bp.save_end[p] : 0u;
@@ -571,11 +576,10 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
     uint32_t hi = end;
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
-    __syncthreads();
     if (hi <= range.x) return;
     int slots[kMaxWaveViews];
 #pragma unroll
-    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = q < n_runs ? s_slot[q] : 0;
+    for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = tk.slot[q];
     const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
     float *drec = reinterpret_cast<float *>(bp.d_rec + (int64_t)tk.cluster * bp.M);
     float *dmean = reinterpret_cast<float *>(bp.d_mean2d);
@@ -648,16 +652,15 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
 {
     if (n_tasks == 0) return hipSuccess;
-    const int per = (n_tasks + 7) / 8;
-    const dim3 grid((unsigned)(8 * per)), block(kWave);
+    const dim3 grid(xcd_grid(n_tasks)), block(kWave);
     if (bp.work && bp.save_T)
-        hipLaunchKernelGGL((blend_remap_kernel<true, true>), grid, block, 0, s, bp, tasks, n_tasks, per);
+        hipLaunchKernelGGL((blend_remap_kernel<true, true>), grid, block, 0, s, bp, tasks, n_tasks);
     else if (bp.work)
-        hipLaunchKernelGGL((blend_remap_kernel<true, false>), grid, block, 0, s, bp, tasks, n_tasks, per);
+        hipLaunchKernelGGL((blend_remap_kernel<true, false>), grid, block, 0, s, bp, tasks, n_tasks);
     else if (bp.save_T)
-        hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks, per);
+        hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks);
     else
-        hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks, per);
+        hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks);
     return hipGetLastError();
 }
 
@@ -678,8 +681,7 @@ hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s)
 hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
 {
     if (n_tasks == 0) return hipSuccess;
-    const int per = (n_tasks + 7) / 8;
-    hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)(8 * per)), dim3(kWave), 0, s, bp, tasks, n_tasks, per);
+    hipLaunchKernelGGL(blend_backward_kernel, dim3(xcd_grid(n_tasks)), dim3(kWave), 0, s, bp, tasks, n_tasks);
     return hipGetLastError();
 }
 

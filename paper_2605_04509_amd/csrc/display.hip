@@ -135,8 +135,8 @@ hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_
 // tile; `emit` selects counting or writing.
 template <bool kEmit>
 __global__ void __launch_bounds__(64) task_kernel(const uint16_t *V, const uint32_t *psi,
-                                                  const int32_t *view_cluster, int W, int H, int tw,
-                                                  int th, int T, uint32_t *counts,
+                                                  const int32_t *view_cluster, const int32_t *view_slot, int W,
+                                                  int H, int tw, int th, int T, uint32_t *counts,
                                                   const uint32_t *offsets, Task *tasks)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,7 +144,8 @@ __global__ void __launch_bounds__(64) task_kernel(const uint16_t *V, const uint3
     const TileGeom g = tile_geom(t, W, H, tw, th);
     const int n = 3 * g.w * g.h;
     uint32_t nt = 0;
-    int cur = -2, cnt = 0, nviews = 0, last_v = -1, start = 0;
+    int cur = -2, cnt = 0, nviews = 0, last_v = -1;
+    Task tk{};
     Task *out = kEmit ? tasks + offsets[t] : nullptr;
     for (int r = 0; r < n; ++r) {
         const int v = V[psi[g.off + r]];
@@ -152,22 +153,32 @@ __global__ void __launch_bounds__(64) task_kernel(const uint16_t *V, const uint3
         if (c < 0) continue;
         const bool new_view = v != last_v;
         if (c != cur || cnt == kWave || (new_view && nviews == kMaxWaveViews)) {
-            if (kEmit && cur >= 0) out[nt - 1] = Task{(uint32_t)t, (uint32_t)cur, (uint32_t)(g.off + start), (uint32_t)cnt};
+            if (kEmit && cur >= 0) out[nt - 1] = tk;
             ++nt;
             cur = c;
             cnt = 0;
             nviews = 0;
             last_v = -1;
-            start = r;
+            tk = Task{};
+            tk.tile = (uint32_t)t;
+            tk.cluster = (uint32_t)c;
+            tk.start = (uint32_t)(g.off + r);
+            for (int q = 0; q < 4; ++q) tk.run_start[q] = (uint8_t)kWave;
         }
         if (v != last_v) {
+            if (kEmit) {
+                tk.run_start[nviews] = (uint8_t)cnt;
+                tk.slot[nviews] = (uint16_t)view_slot[v];
+            }
             ++nviews;
             last_v = v;
         }
         ++cnt;
+        tk.count = (uint16_t)cnt;
+        tk.n_runs = (uint16_t)nviews;
     }
     if (kEmit) {
-        if (cur >= 0) out[nt - 1] = Task{(uint32_t)t, (uint32_t)cur, (uint32_t)(g.off + start), (uint32_t)cnt};
+        if (cur >= 0) out[nt - 1] = tk;
     } else {
         counts[t] = nt;
     }
@@ -178,16 +189,17 @@ hipError_t launch_task_count(const uint16_t *V, const uint32_t *psi, const int32
 {
     const int T = ((W + tw - 1) / tw) * ((H + th - 1) / th);
     hipLaunchKernelGGL(task_kernel<false>, dim3((T + 63) / 64), dim3(64), 0, s, V, psi, view_cluster,
-                       W, H, tw, th, T, counts, (const uint32_t *)nullptr, (Task *)nullptr);
+                       (const int32_t *)nullptr, W, H, tw, th, T, counts, (const uint32_t *)nullptr,
+                       (Task *)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_t *view_cluster,
-                            int W, int H, int tw, int th, const uint32_t *offsets, Task *tasks,
-                            hipStream_t s)
+                            const int32_t *view_slot, int W, int H, int tw, int th, const uint32_t *offsets,
+                            Task *tasks, hipStream_t s)
 {
     const int T = ((W + tw - 1) / tw) * ((H + th - 1) / th);
-    hipLaunchKernelGGL(task_kernel<true>, dim3((T + 63) / 64), dim3(64), 0, s, V, psi, view_cluster,
+    hipLaunchKernelGGL(task_kernel<true>, dim3((T + 63) / 64), dim3(64), 0, s, V, psi, view_cluster, view_slot,
                        W, H, tw, th, T, (uint32_t *)nullptr, offsets, tasks);
     return hipGetLastError();
 }

@@ -52,12 +52,21 @@ struct GradRec {
 
 // A blend work item: up to 64 subpixels of one tile that all belong to one
 // cluster and to at most kMaxWaveViews distinct views, contiguous in Psi.
-struct Task {
+// Psi is sorted by view inside a tile, so the lanes of a task form at most
+// kMaxWaveViews runs of one view each; the task records where each run
+// starts and the compact mean slot of its view, so the blend needs neither
+// the view map nor the slot table per lane.
+struct alignas(16) Task {
     uint32_t tile;
-    uint32_t cluster;  // compact cluster index
-    uint32_t start;    // first position in Psi
-    uint32_t count;    // 1..64
+    uint32_t cluster;      // compact cluster index
+    uint32_t start;        // first position in Psi
+    uint16_t count;        // 1..64
+    uint16_t n_runs;       // distinct views, 1..kMaxWaveViews
+    uint8_t run_start[4];  // first lane of run q; 64 for q >= n_runs
+    uint16_t slot[4];      // compact mean slot of run q's view (0 for q >= n_runs)
+    uint32_t pad;
 };
+static_assert(sizeof(Task) == 32, "Task must be 32 bytes");
 
 // Per-render cluster/view tables (device copies live in the context).
 struct ViewTables {
@@ -154,8 +163,8 @@ hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_
 hipError_t launch_task_count(const uint16_t *V, const uint32_t *psi, const int32_t *view_cluster,
                              int W, int H, int tw, int th, uint32_t *counts, hipStream_t s);
 hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_t *view_cluster,
-                            int W, int H, int tw, int th, const uint32_t *offsets, Task *tasks,
-                            hipStream_t s);
+                            const int32_t *view_slot, int W, int H, int tw, int th, const uint32_t *offsets,
+                            Task *tasks, hipStream_t s);
 
 // Per (cluster, Gaussian) binning record, written by the projection: the
 // tile boxes of the Gaussian in each of the cluster's views (boxes in tile

@@ -3,10 +3,14 @@
 // the 2D covariance, depth and SH colour once per cluster, at the cluster's
 // representative view.
 //
-// Layout: one thread per Gaussian.  It loads the Gaussian's parameters once
-// (SH coefficients stay in registers), builds the 3D covariance once, and
-// then loops over the projected views (means) and clusters (full records),
-// writing each output plane [slot][M] coalesced across the wavefront.
+// Layout: one thread per Gaussian.  A block first copies its Gaussians' SH
+// coefficients into LDS with coalesced loads (rows of odd pitch, so the
+// per-thread reads that follow are free of bank conflicts); each thread
+// then builds the 3D covariance once and loops over the projected views
+// (means) and clusters (full records), writing each output plane [slot][M]
+// coalesced across the wavefront.  A (cluster, Gaussian) whose boxes miss
+// the panel in every view of the cluster gets the "invalid" depth key and no
+// record: it sorts last and is never binned.
 //
 // Arithmetic is IEEE double with FMA contraction disabled (the library is
 // built with -ffp-contract=off); results are rounded to float32 once, when
@@ -208,8 +212,11 @@ struct GaussIn {
     bool finite;
 };
 
+// Parameters of Gaussian i; the SH coefficients are copied to shc from the
+// scene, or (from_scene false) are already there and only checked.
 template <int DEG>
-__device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, float *shc)
+__device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, float *shc,
+                                     bool from_scene = true)
 {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     bool fin = true;
@@ -229,7 +236,7 @@ __device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, 
     const float *s = sc.sh + (int64_t)NB * 3 * i;
 #pragma unroll
     for (int k = 0; k < NB * 3; ++k) {
-        shc[k] = s[k];
+        if (from_scene) shc[k] = s[k];
         fin = fin && isfinite(shc[k]);
     }
     g.finite = fin;
@@ -250,15 +257,29 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
     return true;
 }
 
+constexpr int kProjBlock = 256;
+
 template <int DEG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
+__global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
                                                       int n_clusters, const int32_t *__restrict__ cluster_cam,
                                                       int n_views, const int32_t *__restrict__ view_cam,
                                                       ProjectOut out)
 {
-    constexpr int NB = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NS = (DEG + 1) * (DEG + 1) * 3;  // SH floats per Gaussian
+    constexpr int PITCH = NS | 1;
+    __shared__ float s_sh[kProjBlock * PITCH];
+    const int64_t i0 = (int64_t)blockIdx.x * kProjBlock;
+    const int64_t i = i0 + threadIdx.x;
     const int64_t M = sc.M, Mp = out.Mp;
+    {
+        const int64_t nb = M - i0 < kProjBlock ? (M - i0 > 0 ? M - i0 : 0) : kProjBlock;
+        const float *src = sc.sh + i0 * NS;
+        for (int e = threadIdx.x; e < (int)nb * NS; e += kProjBlock) {
+            const int r = e / NS;
+            s_sh[r * PITCH + (e - r * NS)] = src[e];
+        }
+    }
+    __syncthreads();
     if (i >= M) {
         // padding of each cluster's depth-key segment: sorts last, never read
         if (i < Mp)
@@ -269,8 +290,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
         return;
     }
     GaussIn g;
-    float shc[NB * 3];
-    load_gaussian<DEG>(sc, i, g, shc);
+    float *shc = s_sh + threadIdx.x * PITCH;
+    load_gaussian<DEG>(sc, i, g, shc, false);
     const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
     const float nanf_ = __builtin_nanf("");
 
@@ -287,43 +308,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
         const MeanProj m = project_mean(c, mx, my, mz, g.finite);
         FullProj f;
         f.valid = false;
-        // the SH coefficients are read again from the scene (cache hits) rather
-        // than held in registers across the loop: fewer registers, more waves
-        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, sc.sh + (int64_t)NB * 3 * i);
+        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
+        bool binned = false;
         if (f.valid) {
-            GaussRec r;
-            r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
-            r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
-            out.rec[idx] = r;
             // tile boxes of the cluster's views: this Gaussian's mean in each
             // view (the same values the per-view mean planes hold) with the
             // cluster's extents
-            ItemRec it;
-            it.i = (uint32_t)i;
-            it.nv = 0;
-            it.flags = 0;
+            // (boxes placed by selects, not by a dynamic index, so that the
+            // record stays in registers)
+            ushort4 rb[kItemViews];
+#pragma unroll
+            for (int q = 0; q < kItemViews; ++q) rb[q] = make_ushort4(1, 0, 1, 0);
+            int nv = 0;
             unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
             for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
                 // this thread wrote the view's mean above (NaN if invalid)
                 const float2 m2 = out.mean2d[(int64_t)tg.cv_list[v] * M + i];
                 ushort4 b;
                 if (isnan(m2.x) || !tile_box(m2, f.ext, tg, b)) continue;
-                if (it.nv < kItemViews) it.r[it.nv++] = b;
-                else it.flags = 1;
+#pragma unroll
+                for (int q = 0; q < kItemViews; ++q)
+                    if (q == nv) rb[q] = b;
+                ++nv;
                 x0 = min(x0, b.x);
                 x1 = max(x1, b.y);
                 y0 = min(y0, b.z);
                 y1 = max(y1, b.w);
             }
-            it.bbox = make_ushort4(x0, x1, y0, y1);
-            for (int q = it.nv; q < kItemViews; ++q) it.r[q] = make_ushort4(1, 0, 1, 0);
-            out.items[idx] = it;
-            out.dkey[kidx] = __float_as_uint(m.depth);
-        } else {
-            out.dkey[kidx] = 0xFFFFFFFFu;
+            if (nv != 0) {
+                ItemRec it;
+                it.i = (uint32_t)i;
+                it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
+                it.flags = nv > kItemViews ? 1 : 0;
+                it.bbox = make_ushort4(x0, x1, y0, y1);
+#pragma unroll
+                for (int q = 0; q < kItemViews; ++q) it.r[q] = rb[q];
+                out.items[idx] = it;
+                GaussRec r;
+                r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
+                r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
+                out.rec[idx] = r;
+                binned = true;
+            }
         }
+        out.dkey[kidx] = binned ? __float_as_uint(m.depth) : 0xFFFFFFFFu;
     }
 }
 
@@ -368,7 +398,7 @@ hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileG
 {
     const int64_t n = sc.M > out.Mp ? sc.M : out.Mp;
     if (n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((n + kProjBlock - 1) / kProjBlock)), block(kProjBlock);
     switch (sc.deg) {
     case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
     case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
