@@ -17,7 +17,7 @@ using namespace lfr;
 // First depth chunk: max(kFirstChunk, M / kFirstChunkDiv) ranks per cluster;
 // each following chunk is 4x longer.
 constexpr int64_t kFirstChunk = 4096;
-constexpr int64_t kFirstChunkDiv = 256;
+constexpr int64_t kFirstChunkDiv = 64;
 
 namespace {
 

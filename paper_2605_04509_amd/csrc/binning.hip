@@ -36,9 +36,41 @@ __device__ inline bool rect_alive(const BinParams &bp, int k, ushort4 b)
     return S[y1 * pitch + x1] - S[y0 * pitch + x1] - S[y1 * pitch + x0] + S[y0 * pitch + x0] != 0u;
 }
 
-// Tiles of the item in unit u: the OR of its views' boxes (or its bounding
-// box when it has more boxes than the record holds) in that row and word,
-// restricted to alive lists.  Also returns the unit's row and word.
+// Pixel columns [c0, c1] whose centres in pixel rows [y0, y1] can lie in the
+// cutoff ellipse E <= E_c of record r at mean m, E = a (dx + beta dy)^2 + g dy^2.
+// For dy in an interval inside |dy| <= sqrt(E_c / g), the ellipse's right
+// edge -beta dy + sqrt((E_c - g dy^2) / a) is concave and peaks at
+// dy* = -beta sqrt(E_c / S) / g, S = 1/a + beta^2/g (where the edge reaches
+// the full half width sqrt(E_c S)); the left edge is its mirror image.  So
+// the extremes over the row band are at dy* clamped into it.  E_c is the
+// record's cutoff widened by 0.1% and 1e-3, and the span by 1e-4 relative
+// and 0.02 px: margins far above the float32 error of this evaluation and of
+// the blend's.  Returns false when no centre of the band can be inside.
+__device__ inline bool row_span(const ItemRec &r, float2 m, int y0, int y1, int W, int &c0, int &c1)
+{
+    const float Ec = r.ecut * 1.001f + 1e-3f;
+    const float hy = sqrtf(Ec / r.g);
+    const float lo = fmaxf((float)y0 + 0.5f - m.y, -hy), hi = fminf((float)y1 + 0.5f - m.y, hy);
+    if (!(lo <= hi)) return false;
+    const float S = 1.0f / r.a + r.beta * r.beta / r.g;
+    const float ds = -r.beta * sqrtf(Ec / S) / r.g;
+    const float t1 = fminf(fmaxf(ds, lo), hi), t2 = fminf(fmaxf(ds, -hi), -lo);
+    const float xr = -r.beta * t1 + sqrtf(fmaxf(Ec - r.g * t1 * t1, 0.0f) / r.a);
+    const float xl = r.beta * t2 - sqrtf(fmaxf(Ec - r.g * t2 * t2, 0.0f) / r.a);
+    const float pad = 1e-4f * fmaxf(fabsf(xr), fabsf(xl)) + 0.02f;
+    // pixel x is covered when its centre x + 0.5 lies in [m.x + xl, m.x + xr]
+    const float f0 = fmaxf(ceilf(m.x + xl - pad - 0.5f), 0.0f);
+    const float f1 = fminf(floorf(m.x + xr + pad - 0.5f), (float)(W - 1));
+    if (!(f0 <= f1)) return false;
+    c0 = (int)f0;
+    c1 = (int)f1;
+    return true;
+}
+
+// Tiles of the item in unit u: the OR over its views of the tiles in the
+// unit's row and word that the view's ellipse span covers (or the bounding
+// box when the record holds too few views), restricted to alive lists.
+// Also returns the unit's row and word.
 __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &r, int u, int &ty, int &w)
 {
     const int w0 = (int)r.bbox.x >> 5;
@@ -46,16 +78,23 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &
     ty = (int)r.bbox.z + u / nw;
     w = w0 + u % nw;
     const int xb = w << 5;
-    uint32_t m = 0;
-    const int nb = r.flags ? 1 : (int)r.nv;
-    for (int v = 0; v < nb; ++v) {
-        const ushort4 b = r.flags ? r.bbox : r.r[v];
-        if (ty < (int)b.z || ty > (int)b.w) continue;
-        const int lo = (int)b.x - xb, hi = (int)b.y - xb;
-        if (hi < 0 || lo > 31) continue;
+    auto bits = [&](int lo, int hi) -> uint32_t {  // tiles [lo, hi] within the word
+        lo -= xb;
+        hi -= xb;
+        if (hi < 0 || lo > 31) return 0u;
         const uint32_t mh = hi >= 31 ? 0xFFFFFFFFu : ((2u << hi) - 1u);
         const uint32_t ml = lo <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << lo);
-        m |= mh & ml;
+        return mh & ml;
+    };
+    uint32_t m = 0;
+    if (r.flags) {
+        m = bits((int)r.bbox.x, (int)r.bbox.y);
+    } else {
+        const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
+        for (int v = 0; v < (int)r.nv; ++v) {
+            int c0, c1;
+            if (row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 / bp.tw, c1 / bp.tw);
+        }
     }
     const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;
     return m & alive_k[(int64_t)ty * bp.alive_words + w];

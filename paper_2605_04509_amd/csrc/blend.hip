@@ -315,8 +315,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
                             n_live += (lane == 0 && __ballot(pass & (T > 0.0f)) != 0) ? 1u : 0u;
                             stopl = stop ? s_pos[g] + 1u : stopl;
                         }
-                        const float Cb = C + T * bgu;
-                        C = take ? fmaf(CU[gk] * alpha, T, C) : (stop ? Cb : C);
+                        // branch-free update: fma(0, T, C) = C for a lane that does not take
+                        const float wgt = take ? CU[gk] * alpha : 0.0f;
+                        const float Ct = fmaf(wgt, T, C);
+                        C = stop ? C + T * bgu : Ct;
                         if (kSave) {
                             endp = take ? s_pos[g] + 1u : endp;
                             Tsave = stop ? T : (take ? Tn : Tsave);

@@ -167,17 +167,21 @@ hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_
                             Task *tasks, hipStream_t s);
 
 // Per (cluster, Gaussian) binning record, written by the projection: the
-// tile boxes of the Gaussian in each of the cluster's views (boxes in tile
-// units, inclusive; up to kItemViews non-empty boxes) and their union's
-// bounding box.  With more non-empty boxes than fit, `flags` bit 0 is set and
-// binning uses the bounding box (still a conservative cover).  64 B aligned.
-constexpr int kItemViews = 6;
+// union bounding box of the Gaussian's tile boxes over the cluster's views
+// (tile units, inclusive), the conic and cutoff exponent the blend uses, and
+// the 2D mean in each view whose box is non-empty (up to kItemViews).  Binning
+// covers, per tile row and view, the x-range of the cutoff ellipse over that
+// row; with more non-empty views than fit, `flags` bit 0 is set and binning
+// covers the bounding box (still conservative).  64 B aligned.
+constexpr int kItemViews = 4;
 struct alignas(64) ItemRec {
-    uint32_t i;
     uint16_t nv;
     uint16_t flags;
+    float ecut;                // log2(255 o) + 0.01: alpha < 1/255 beyond it
     ushort4 bbox;              // x0, x1, y0, y1
-    ushort4 r[kItemViews];     // x0, x1, y0, y1 per non-empty view box
+    float a, beta, g;          // conic: E = a (dx + beta dy)^2 + g dy^2
+    float pad;
+    float2 m[kItemViews];      // mean in each view with a non-empty box
 };
 static_assert(sizeof(ItemRec) == 64, "ItemRec must be 64 bytes");
 

@@ -316,11 +316,11 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
             // tile boxes of the cluster's views: this Gaussian's mean in each
             // view (the same values the per-view mean planes hold) with the
             // cluster's extents
-            // (boxes placed by selects, not by a dynamic index, so that the
+            // (means placed by selects, not by a dynamic index, so that the
             // record stays in registers)
-            ushort4 rb[kItemViews];
+            float2 mv[kItemViews];
 #pragma unroll
-            for (int q = 0; q < kItemViews; ++q) rb[q] = make_ushort4(1, 0, 1, 0);
+            for (int q = 0; q < kItemViews; ++q) mv[q] = make_float2(0.f, 0.f);
             int nv = 0;
             unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
             for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
                 if (isnan(m2.x) || !tile_box(m2, f.ext, tg, b)) continue;
 #pragma unroll
                 for (int q = 0; q < kItemViews; ++q)
-                    if (q == nv) rb[q] = b;
+                    if (q == nv) mv[q] = m2;
                 ++nv;
                 x0 = min(x0, b.x);
                 x1 = max(x1, b.y);
@@ -339,12 +339,16 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
             }
             if (nv != 0) {
                 ItemRec it;
-                it.i = (uint32_t)i;
                 it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
                 it.flags = nv > kItemViews ? 1 : 0;
+                it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
                 it.bbox = make_ushort4(x0, x1, y0, y1);
+                it.a = f.conic[0];
+                it.beta = f.conic[1];
+                it.g = f.conic[2];
+                it.pad = 0.0f;
 #pragma unroll
-                for (int q = 0; q < kItemViews; ++q) it.r[q] = rb[q];
+                for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
                 out.items[idx] = it;
                 GaussRec r;
                 r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
