@@ -532,18 +532,63 @@ __device__ __forceinline__ float dpp_get(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes, returned in every lane: DPP butterflies inside each
-// 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
-// row_mirror), then the four row sums through two lane swaps.
-__device__ __forceinline__ float wave_sum(float v)
+// Value of lane (lane ^ m) for m = 1, 2, 4, 8 with DPP inside 16-lane rows
+// (quad permutations for 1 and 2, a row shift in the lane's direction for 4
+// and 8), and through a lane permute for 16 and 32.
+// (Both row shifts are computed by every lane before the select: a DPP read
+// in a divergent branch would read lanes the branch has switched off.)
+template <int m>
+__device__ __forceinline__ float lane_xor(float v, int lane)
 {
-    v += dpp_get<0xB1>(v);
-    v += dpp_get<0x4E>(v);
-    v += dpp_get<0x141>(v);
-    v += dpp_get<0x140>(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
+    if constexpr (m == 1) {
+        return dpp_get<0xB1>(v);
+    } else if constexpr (m == 2) {
+        return dpp_get<0x4E>(v);
+    } else if constexpr (m == 4) {
+        const float from_below = dpp_get<0x114>(v), from_above = dpp_get<0x104>(v);
+        return (lane & 4) ? from_below : from_above;
+    } else if constexpr (m == 8) {
+        const float from_below = dpp_get<0x118>(v), from_above = dpp_get<0x108>(v);
+        return (lane & 8) ? from_below : from_above;
+    } else {
+        return __shfl_xor(v, m, 64);
+    }
+}
+
+// One halving step of a transposed reduction: lanes with bit m set keep the
+// upper half of their n values, the others the lower half, each adding the
+// half its partner (lane ^ m) gives away.
+template <int m, int n>
+__device__ __forceinline__ void halve(float (&v)[16], int lane)
+{
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int j = 0; j < n / 2; ++j) {
+        const float keep = up ? v[j + n / 2] : v[j];
+        const float give = up ? v[j] : v[j + n / 2];
+        v[j] = keep + lane_xor<m>(give, lane);
+    }
+}
+
+// Sums of 16 per-lane values over the wavefront: after halving steps on
+// lane bits 0..3 each lane holds one value index's sum over its 16-lane
+// row, and two more exchanges add the four rows.  Lane l ends with the sum
+// of value (bit-reversed l & 15).
+__device__ __forceinline__ float wave_sum16(float (&v)[16], int lane)
+{
+    halve<1, 16>(v, lane);
+    halve<2, 8>(v, lane);
+    halve<4, 4>(v, lane);
+    halve<8, 2>(v, lane);
+    float r = v[0];
+    r += lane_xor<16>(r, lane);
+    r += lane_xor<32>(r, lane);
+    return r;
+}
+
+__device__ __forceinline__ int rev4(int l)
+{
+    return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
 }
 
 __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const Task *__restrict__ tasks,
@@ -623,27 +668,34 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
             const bool smooth = on && st.raw <= kAlphaMax;
             const float dE = -da * st.raw * kLn2;
             const float t2 = 2.0f * a.x * st.w;
-            const float v0 = wave_sum(smooth ? dE * st.w * st.w : 0.0f);    // dA'
-            const float v1 = wave_sum(smooth ? dE * t2 * st.dy : 0.0f);     // dbeta
-            const float v2 = wave_sum(smooth ? dE * st.dy * st.dy : 0.0f);  // dG'
-            const float v3 = wave_sum(smooth ? da * st.ex : 0.0f);          // do
-            const float v4 = wave_sum(u == 0 ? dc : 0.0f);                  // dr
-            const float v5 = wave_sum(u == 1 ? dc : 0.0f);                  // dg
-            const float v6 = wave_sum(u == 2 ? dc : 0.0f);                  // db
-            const uint32_t i = s_i[g];
-            const float vr = lane == 0 ? v0 : lane == 1 ? v1 : lane == 2 ? v2 : lane == 3 ? v3
-                           : lane == 4 ? v4 : lane == 5 ? v5 : v6;
-            if (lane < 7) unsafeAtomicAdd(drec + (int64_t)i * 8 + lane, vr);
             // the mean of the lane's view: d/dmean = -d/d(dx, dy)
             const float dmx = smooth ? -dE * t2 : 0.0f;
             const float dmy = smooth ? -dE * fmaf(t2, a.y, 2.0f * a.z * st.dy) : 0.0f;
+            // values 0..6: record derivatives dA', dbeta, dG', do, dr, dg, db;
+            // 8 + 2q, 9 + 2q: mean derivatives of the task's view q
+            float v[16];
+            v[0] = smooth ? dE * st.w * st.w : 0.0f;
+            v[1] = smooth ? dE * t2 * st.dy : 0.0f;
+            v[2] = smooth ? dE * st.dy * st.dy : 0.0f;
+            v[3] = smooth ? da * st.ex : 0.0f;
+            v[4] = u == 0 ? dc : 0.0f;
+            v[5] = u == 1 ? dc : 0.0f;
+            v[6] = u == 2 ? dc : 0.0f;
+            v[7] = 0.0f;
 #pragma unroll
             for (int q = 0; q < kMaxWaveViews; ++q) {
-                if (q >= n_runs) break;
-                const float sx = wave_sum(my_run == q ? dmx : 0.0f);
-                const float sy = wave_sum(my_run == q ? dmy : 0.0f);
-                if (lane < 2 && (sx != 0.0f || sy != 0.0f))
-                    unsafeAtomicAdd(dmean + ((int64_t)slots[q] * bp.M + i) * 2 + lane, lane == 0 ? sx : sy);
+                v[8 + 2 * q] = my_run == q ? dmx : 0.0f;
+                v[9 + 2 * q] = my_run == q ? dmy : 0.0f;
+            }
+            const float sum = wave_sum16(v, lane);
+            const uint32_t i = s_i[g];
+            const int idx = rev4(lane & 15);
+            if (lane < 16 && idx < 7) {
+                unsafeAtomicAdd(drec + (int64_t)i * 8 + idx, sum);
+            } else if (lane < 16 && idx >= 8) {
+                const int q = (idx - 8) >> 1;
+                if (q < n_runs && sum != 0.0f)
+                    unsafeAtomicAdd(dmean + ((int64_t)slots[q] * bp.M + i) * 2 + (idx & 1), sum);
             }
         }
         __syncthreads();
