@@ -518,6 +518,29 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     return LFR_OK;
 }
 
+// Launch order of the blend work items: cluster by cluster, and inside a
+// cluster by blocks of kTaskBlock x kTaskBlock tiles (row-major blocks,
+// row-major tiles inside a block), so that the items that read the same
+// Gaussians' records (one cluster, neighbouring tiles) run close together.
+constexpr int kTaskBlock = 4;
+
+lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, int n)
+{
+    if (n <= 1) return LFR_OK;
+    std::vector<Task> h(n);
+    HIPCHK(ctx, hipMemcpy(h.data(), d_tasks, sizeof(Task) * n, hipMemcpyDeviceToHost));
+    const int nbx = (d->TX + kTaskBlock - 1) / kTaskBlock;
+    auto key = [&](const Task &t) {
+        const int ty = (int)t.tile / d->TX, tx = (int)t.tile % d->TX;
+        const uint64_t blk = (uint64_t)(ty / kTaskBlock) * nbx + (uint64_t)(tx / kTaskBlock);
+        const uint64_t in = (uint64_t)(ty % kTaskBlock) * kTaskBlock + (uint64_t)(tx % kTaskBlock);
+        return ((uint64_t)t.cluster << 48) | (blk << 16) | in;
+    };
+    std::stable_sort(h.begin(), h.end(), [&](const Task &a, const Task &b) { return key(a) < key(b); });
+    HIPCHK(ctx, hipMemcpy(d_tasks, h.data(), sizeof(Task) * n, hipMemcpyHostToDevice));
+    return LFR_OK;
+}
+
 // Blend work items and per-(tile, cluster) subpixel counts for cluster
 // size S, built once per display.
 lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
@@ -558,6 +581,7 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
                                  ts.d_tasks, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ts.n = (int)n;
+    CHK(order_tasks(ctx, d, ts.d_tasks, ts.n));
     (void)hipFree(vslot);
     (void)hipFree(cnt);
     (void)hipFree(off);

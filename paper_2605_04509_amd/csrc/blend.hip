@@ -694,8 +694,10 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
                 unsafeAtomicAdd(drec + (int64_t)i * 8 + idx, sum);
             } else if (lane < 16 && idx >= 8) {
                 const int q = (idx - 8) >> 1;
+                // (selects, not slots[q]: a per-lane index could put the array in scratch)
+                const int sq = q == 0 ? slots[0] : q == 1 ? slots[1] : q == 2 ? slots[2] : slots[3];
                 if (q < n_runs && sum != 0.0f)
-                    unsafeAtomicAdd(dmean + ((int64_t)slots[q] * bp.M + i) * 2 + (idx & 1), sum);
+                    unsafeAtomicAdd(dmean + ((int64_t)sq * bp.M + i) * 2 + (idx & 1), sum);
             }
         }
         __syncthreads();
