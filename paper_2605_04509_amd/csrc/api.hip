@@ -496,7 +496,7 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
     CHK(ws_get_t(ctx, kPairV1, P, &pv1));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.Mp * bp.n_clusters))),
                &sort_temp));
-    HIPCHK(ctx, launch_chunk_emit(bp, pr.dks, pr.dvs, r0, len, offsets, P, pk0, pv0, s));
+    HIPCHK(ctx, launch_chunk_emit(bp, pr.dks, pr.dvs, r0, len, counts, offsets, P, pk0, pv0, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStKeygen, e0, e1);
     bool palt = false;

@@ -169,9 +169,15 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     const ItemRec *items_k = bp.items + (int64_t)k * bp.M;
     uint32_t i = 0;
     int U = 0;
-    if (in) {
+    // a cluster without any list that still has unsaturated subpixels emits
+    // nothing (the summed-area table's total)
+    const bool cluster_alive =
+        !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
+    if (in && cluster_alive) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
-        if (dkey_sorted[e] != 0xFFFFFFFFu) {
+        // (the emitting pass skips items the counting pass found empty
+        // without reading their records: most items of late chunks)
+        if (dkey_sorted[e] != 0xFFFFFFFFu && (!kEmit || counts[o] != 0u)) {
             i = dval_sorted[e];
             const ItemRec &it = items_k[i];
             // items whose tiles are all saturated emit nothing: skip their units
@@ -326,13 +332,13 @@ hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, 
 }
 
 hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                             int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs, uint32_t *pair_keys,
-                             uint32_t *pair_vals, hipStream_t s)
+                             int64_t r0, int64_t len, const uint32_t *counts, const uint32_t *offsets,
+                             uint64_t n_pairs, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s)
 {
     if (len == 0 || bp.n_clusters == 0 || n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(chunk_tiles_kernel<true>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp,
-                       dkey_sorted, dval_sorted, r0, len, (uint32_t *)nullptr, offsets, n_pairs, pair_keys,
-                       pair_vals);
+                       dkey_sorted, dval_sorted, r0, len, const_cast<uint32_t *>(counts), offsets, n_pairs,
+                       pair_keys, pair_vals);
     return hipGetLastError();
 }
 

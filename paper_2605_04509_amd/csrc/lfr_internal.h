@@ -247,9 +247,10 @@ struct BinParams {
 };
 hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
                               int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
+// counts: the counting pass's per-item pair counts (items with none are skipped).
 hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                             int64_t r0, int64_t len, const uint32_t *offsets, uint64_t n_pairs,
-                             uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
+                             int64_t r0, int64_t len, const uint32_t *counts, const uint32_t *offsets,
+                             uint64_t n_pairs, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // With dP, the pair count is min(*dP, P) read on the device (P sizes the grid).
 hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s,
