@@ -376,7 +376,9 @@ def main():
                  "achieved": flops / bl / (blend_ms * 1e-3) / 1e12, "peak": PEAK_FP32_NONPACKED_TFLOPS,
                  "unit": "TFLOP/s", "evals": work["evals"], "blended": work["blended"],
                  "wave_steps": work["wave_steps"], "wave_steps_live": work["wave_steps_live"],
-                 "lane_utilization": work["evals"] / max(1, 64 * work["wave_steps"]),
+                 # lane slots the kernel walks (staged Gaussians x 64) per alpha the
+                 # method evaluates: below 1 where the per-batch culling drops entries
+                 "lane_slots_per_eval": 64 * work["wave_steps"] / max(1, work["evals"]),
                  "traffic": measured_traffic("blend_remap_kernel<false>", w.name,
                                                (params.tile_w, params.tile_h))}
     blend_alu["frac"] = blend_alu["achieved"] / blend_alu["peak"]
