@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -145,6 +146,13 @@ def fwd_bwd(args, torch, lfr, sync):
             "pairs": st["pairs"], "loss": loss, "steps": args.bwd_steps}
 
 
+def psnr_db(torch, img, ref):
+    """PSNR (dB, peak 1) of an interlaced image against a reference image, both
+    clamped to [0, 1] as a display shows them, over every subpixel."""
+    mse = float(((img.clamp(0.0, 1.0) - ref.clamp(0.0, 1.0)).double() ** 2).mean())
+    return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+
+
 def paper_shapes(args, torch, lfr, sync):
     """The paper's two display shapes on the 3M-Gaussian scene: 71 views over
     53 degrees at 3840x2160 with reuse groups of 18, and 63 views over 53
@@ -159,9 +167,11 @@ def paper_shapes(args, torch, lfr, sync):
         ctx = lfr.Context(0)
         ds = lfr.DeviceScene.from_numpy(w.make_scene(), device="cuda:0")
         cams = lfr.cameras_array(pack_cameras(w.cameras()))
-        out = torch.empty((w.display.height, w.display.width, 3), dtype=torch.float32, device="cuda:0")
+        imgs = {}
         r = {"display": [w.display.width, w.display.height, w.display.num_views], "span_deg": w.span_deg}
         for label, cs in (("reuse+remap", S), ("exact", 1)):
+            out = torch.empty((w.display.height, w.display.width, 3), dtype=torch.float32, device="cuda:0")
+            imgs[label] = out
             best, _ = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(cs,), reps=1)
             d = lfr.Display(ctx, w.display.with_tile(best["tile_w"], best["tile_h"]))
             fn = lambda: lfr.render(ctx, d, ds, cams, cluster_size=cs, out=out)
@@ -170,6 +180,8 @@ def paper_shapes(args, torch, lfr, sync):
             r[label] = {"cluster_size": cs, "tile": [best["tile_w"], best["tile_h"]], "ms": t * 1e3,
                         "frames_per_s": 1.0 / t}
             if label == "exact":
+                sync()
+                r["reuse+remap"]["psnr_vs_exact_db"] = psnr_db(torch, imgs["reuse+remap"], imgs["exact"])
                 plain = None
                 for vb in (18, 36):
                     fp = lambda vb=vb: lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=vb, out=out,
@@ -413,6 +425,20 @@ def main():
         "views": work["views"],
         "roofline": roofline, "roofline_other": other, "fwd_bwd_ms": None,
     }
+
+    # image quality of the reuse path: PSNR of the cluster-size-S image (and of
+    # the paper's other group sizes) against the exact path (S = 1)
+    exact = torch.empty_like(out)
+    lfr.render(ctx, disp, ds, cams, cluster_size=1, out=exact)
+    psnr = {}
+    for cs in sorted({2, 4, 8, S}):
+        img = torch.empty_like(out)
+        lfr.render(ctx, disp, ds, cams, cluster_size=cs, out=img)
+        sync()
+        psnr[str(cs)] = psnr_db(torch, img, exact)
+        del img
+    result["psnr_vs_exact_db"] = psnr
+    log("PSNR vs exact (dB) by cluster size", psnr)
 
     if not args.no_ablation:
         # the paper's ablation modes, each on its own fastest tile shape
