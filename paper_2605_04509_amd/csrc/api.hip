@@ -25,7 +25,7 @@ enum Slot {
     kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
-    kAliveSat, kNumSlots
+    kAliveSat, kItemBox, kNumSlots
 };
 
 struct Buf {
@@ -343,6 +343,7 @@ struct Projected {
     int64_t Mp = 0;             // stride of the depth-sorted per-cluster segments
     GaussRec *rec = nullptr;
     ItemRec *items = nullptr;
+    ushort4 *ibox = nullptr;
     float2 *mean2d = nullptr;
     const uint32_t *dks = nullptr;
     const uint32_t *dvs = nullptr;
@@ -387,6 +388,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
     CHK(ws_get_t(ctx, kItems, MK, &po.items));
+    CHK(ws_get_t(ctx, kItemBox, MK, &po.ibox));
     CHK(ws_get_t(ctx, kDKey0, MKp, &po.dkey));
     CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
     CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
@@ -403,6 +405,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
     out->items = po.items;
+    out->ibox = po.ibox;
     out->mean2d = po.mean2d;
     out->dks = alt ? dkey1 : po.dkey;
     out->dvs = alt ? dval1 : po.dval;
@@ -413,7 +416,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
 }
 
 BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int64_t Mp, int cbits,
-                     const uint32_t *alive, const ItemRec *items)
+                     const uint32_t *alive, const ItemRec *items, const ushort4 *ibox)
 {
     const Grid *d = &d_;
     BinParams bp;
@@ -432,6 +435,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive = alive;
     bp.alive_words = (d->TX + 31) / 32;
     bp.items = items;
+    bp.ibox = ibox;
     bp.alive_total = nullptr;
     bp.alive_sat = nullptr;
     return bp;
@@ -759,7 +763,7 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
         CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
         CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
     }
-    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items);
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox);
     if (planned) bin.alive_total = &d_tot->alive;
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
@@ -1260,7 +1264,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
-        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items);
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;

@@ -179,9 +179,11 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         // without reading their records: most items of late chunks)
         if (dkey_sorted[e] != 0xFFFFFFFFu && (!kEmit || counts[o] != 0u)) {
             i = dval_sorted[e];
-            const ItemRec &it = items_k[i];
-            // items whose tiles are all saturated emit nothing: skip their units
-            if (!bp.alive_sat || (it.nv != 0 && rect_alive(bp, k, it.bbox))) U = item_units(it);
+            // items whose tiles are all saturated emit nothing: the counting
+            // pass tests the 8-byte union box before it reads the record
+            // (the emitting pass only sees items with pairs)
+            if (kEmit || !bp.alive_sat || rect_alive(bp, k, bp.ibox[(int64_t)k * bp.M + i]))
+                U = item_units(items_k[i]);
         }
     }
     const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);

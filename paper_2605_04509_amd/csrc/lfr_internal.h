@@ -192,7 +192,8 @@ struct SceneDev {
 };
 struct ProjectOut {
     GaussRec *rec;      // [K'][M]
-    ItemRec *items;     // [K'][M]  tile boxes per cluster view
+    ItemRec *items;     // [K'][M]  binning records
+    ushort4 *ibox;      // [K'][M]  the records' union tile boxes (read alone to skip saturated items)
     uint32_t *dkey;     // [K'][Mp] float32 depth bits, 0xFFFFFFFF if invalid or padding
     uint32_t *dval;     // [K'][Mp] Gaussian index
     float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
@@ -242,6 +243,7 @@ struct BinParams {
     const uint32_t *alive;    // [K'][TY][alive_words] bit per (cluster, tile) list still needed
     int alive_words;          // 32-bit words per tile row
     const ItemRec *items;     // [K'][M]
+    const ushort4 *ibox;      // [K'][M] union tile box of each record
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
 };

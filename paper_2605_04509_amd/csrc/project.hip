@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
 #pragma unroll
                 for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
                 out.items[idx] = it;
+                out.ibox[idx] = it.bbox;
                 GaussRec r;
                 r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
                 r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
