@@ -220,6 +220,34 @@ def test_depth_chunking_does_not_change_the_image(lib, tiny_setup, S, remap):
     d.close()
 
 
+@pytest.mark.parametrize("S,first_chunk", [(1, 0), (4, 0), (4, 64), (8, 7)])
+def test_work_counts_agree_across_blend_orders(lib, tiny_setup, S, first_chunk):
+    """The counting renders report the method's work on the binned lists: the
+    alphas each subpixel evaluates up to and including its stop, and the
+    contributions it blends.  Both depend only on the lists, not on the thread
+    order: the remapped blend (which culls staged entries and counts from list
+    positions) and the row-major blend (which walks every entry) must agree
+    exactly, with one depth chunk or several."""
+    lfr, ctx = lib
+    w, scene, cams, V, ds = tiny_setup
+    say("work counts, S =", S, "first chunk", first_chunk)
+    d = _display(lfr, ctx, w.display)
+    counts = {}
+    for remap in (True, False):
+        out = torch.empty((w.display.height, w.display.width, 3), device="cuda:0")
+        lfr.render(ctx, d, ds, cams, cluster_size=S, remap=remap, out=out, count_work=True,
+                   first_chunk=first_chunk)
+        torch.cuda.synchronize()
+        st = ctx.stats()
+        counts[remap] = (st["evals"], st["blended"], st["pairs"], st["chunks"])
+        say(" remap" if remap else " row-major", counts[remap], "wave steps", st["wave_steps"])
+        if remap:
+            assert 0 < st["wave_steps_live"] <= st["wave_steps"]
+    assert counts[True] == counts[False]
+    assert counts[True][0] >= counts[True][1] > 0
+    d.close()
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64)])
 def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     lfr, ctx = lib
