@@ -558,39 +558,52 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
     hipStream_t s = ctx->stream;
     TaskSet ts;
     ts.cluster_bits = bits_for(vt.n_clusters);
+    // device memory of this call: the temporaries are freed on every return,
+    // the task set's arrays on an error return
+    struct Guard {
+        std::vector<void *> tmp, owned;
+        bool keep = false;
+        ~Guard()
+        {
+            for (void *p : tmp) (void)hipFree(p);
+            if (!keep)
+                for (void *p : owned) (void)hipFree(p);
+        }
+    } guard;
+    auto dev_alloc = [&](void **p, size_t bytes, bool owned) -> hipError_t {
+        const hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) (owned ? guard.owned : guard.tmp).push_back(*p);
+        return e;
+    };
     const int64_t n_tc = (int64_t)d->T << ts.cluster_bits;
-    HIPCHK(ctx, hipMalloc(&ts.d_view_cluster, sizeof(int32_t) * d->N));
+    HIPCHK(ctx, dev_alloc((void **)&ts.d_view_cluster, sizeof(int32_t) * d->N, true));
     HIPCHK(ctx, hipMemcpy(ts.d_view_cluster, vt.view_cluster.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMalloc(&ts.d_tc_count, sizeof(uint32_t) * n_tc));
+    HIPCHK(ctx, dev_alloc((void **)&ts.d_tc_count, sizeof(uint32_t) * n_tc, true));
     HIPCHK(ctx, launch_fill_u32(ts.d_tc_count, 0u, n_tc, s));
     HIPCHK(ctx, launch_tc_count(d->d_V, ts.d_view_cluster, d->W, d->H, d->tw, d->th, ts.cluster_bits,
                                 ts.d_tc_count, s));
     uint32_t *cnt = nullptr, *off = nullptr;
     uint64_t *tot = nullptr;
     void *tmp = nullptr;
-    HIPCHK(ctx, hipMalloc(&cnt, sizeof(uint32_t) * d->T));
-    HIPCHK(ctx, hipMalloc(&off, sizeof(uint32_t) * d->T));
-    HIPCHK(ctx, hipMalloc(&tot, sizeof(uint64_t)));
-    HIPCHK(ctx, hipMalloc(&tmp, scan_temp_bytes(d->T)));
+    HIPCHK(ctx, dev_alloc((void **)&cnt, sizeof(uint32_t) * d->T, false));
+    HIPCHK(ctx, dev_alloc((void **)&off, sizeof(uint32_t) * d->T, false));
+    HIPCHK(ctx, dev_alloc((void **)&tot, sizeof(uint64_t), false));
+    HIPCHK(ctx, dev_alloc(&tmp, scan_temp_bytes(d->T), false));
     HIPCHK(ctx, launch_task_count(d->d_V, d->d_psi, ts.d_view_cluster, d->W, d->H, d->tw, d->th, cnt, s));
     HIPCHK(ctx, launch_exclusive_scan(cnt, off, d->T, tmp, tot, s));
     uint64_t n = 0;
     HIPCHK(ctx, hipMemcpyAsync(&n, tot, sizeof n, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    HIPCHK(ctx, hipMalloc(&ts.d_tasks, sizeof(Task) * std::max<uint64_t>(n, 1)));
+    HIPCHK(ctx, dev_alloc((void **)&ts.d_tasks, sizeof(Task) * std::max<uint64_t>(n, 1), true));
     int32_t *vslot = nullptr;
-    HIPCHK(ctx, hipMalloc(&vslot, sizeof(int32_t) * d->N));
+    HIPCHK(ctx, dev_alloc((void **)&vslot, sizeof(int32_t) * d->N, false));
     HIPCHK(ctx, hipMemcpy(vslot, vt.view_slot.data(), sizeof(int32_t) * d->N, hipMemcpyHostToDevice));
     HIPCHK(ctx, launch_task_emit(d->d_V, d->d_psi, ts.d_view_cluster, vslot, d->W, d->H, d->tw, d->th, off,
                                  ts.d_tasks, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ts.n = (int)n;
     CHK(order_tasks(ctx, d, ts.d_tasks, ts.n));
-    (void)hipFree(vslot);
-    (void)hipFree(cnt);
-    (void)hipFree(off);
-    (void)hipFree(tot);
-    (void)hipFree(tmp);
+    guard.keep = true;
     auto ins = d->tasks.emplace(key, ts);
     *out = &ins.first->second;
     return LFR_OK;
@@ -946,12 +959,15 @@ static lfr_status display_finish(lfr_context *ctx, lfr_display *d, lfr_display *
     HIPCHK(ctx, launch_remap(d->d_V, d->W, d->H, d->tw, d->th, d->d_psi, s));
     uint32_t *mask = nullptr;
     HIPCHK(ctx, hipMalloc(&mask, sizeof(uint32_t) * d->N));
+    struct FreeMask {
+        uint32_t *p;
+        ~FreeMask() { (void)hipFree(p); }
+    } free_mask{mask};  // on every return below
     HIPCHK(ctx, launch_fill_u32(mask, 0u, d->N, s));
     HIPCHK(ctx, launch_referenced_views(d->d_V, 3ll * d->W * d->H, mask, s));
     std::vector<uint32_t> hm(d->N);
     HIPCHK(ctx, hipMemcpyAsync(hm.data(), mask, sizeof(uint32_t) * d->N, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    (void)hipFree(mask);
     d->ref.assign(d->N, 0);
     d->n_ref = 0;
     for (int j = 0; j < d->N; ++j)
