@@ -102,7 +102,7 @@ typedef struct {
     uint32_t flags;         /* LFR_* bits above                            */
     float background[3];    /* added as T_final * background per channel   */
     int32_t first_chunk;    /* depth ranks per cluster in the first chunk;
-                               later chunks grow 4x; 0 = max(4096, M/64).
+                               later chunks grow 4x; 0 = max(32768, M/64).
                                Changes only the amount of work, never the
                                image.                                       */
     int32_t fullframe_tile; /* lfr_render_fullframe_interlace only: square

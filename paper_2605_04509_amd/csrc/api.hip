@@ -16,7 +16,7 @@ using namespace lfr;
 
 // First depth chunk: max(kFirstChunk, M / kFirstChunkDiv) ranks per cluster;
 // each following chunk is 4x longer.
-constexpr int64_t kFirstChunk = 4096;
+constexpr int64_t kFirstChunk = 32768;
 constexpr int64_t kFirstChunkDiv = 64;
 
 namespace {
@@ -738,10 +738,15 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     CHK(ws_get_t(ctx, kState, nsub, &state));
     CHK(ws_get_t(ctx, kTaskAlive, (size_t)std::max(ts->n, 1) + 4, &task_alive));
     CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
-    HIPCHK(ctx, launch_copy_u32(tc_alive, ts->d_tc_count, n_tc, s));
-    HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
-    HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
-    HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+    // per-frame traversal state: every list and subpixel unsaturated
+    auto reset_state = [&]() -> lfr_status {
+        HIPCHK(ctx, launch_copy_u32(tc_alive, ts->d_tc_count, n_tc, s));
+        HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
+        HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
+        HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
+        return LFR_OK;
+    };
+    CHK(reset_state());
     uint32_t *alive_sat;
     CHK(ws_get_t(ctx, kAliveSat, (size_t)vt.n_clusters * (d->TY + 1) * (d->TX + 1) + 1, &alive_sat));
 
@@ -779,17 +784,23 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox);
     if (planned) bin.alive_total = &d_tot->alive;
 
-    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
-    // (one chunk holding every rank when the lists are kept for the backward)
-    int64_t r0 = 0, len = save ? std::max<int64_t>(M, 1)
-                          : opts->first_chunk > 0
-                              ? (int64_t)opts->first_chunk
-                              : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x.
+    // The backward needs each subpixel's whole list in one chunk: a render
+    // that keeps its lists first tries the first chunk alone and keeps it if
+    // every subpixel saturated there (the lists then hold every entry any
+    // subpixel reached); otherwise it renders again with one chunk holding
+    // every rank.
+    const int64_t len0 = opts->first_chunk > 0
+                             ? (int64_t)opts->first_chunk
+                             : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    int64_t r0 = 0, len = len0;
     Chunk saved_chunk;
     bool blend_ran = false;
     uint64_t pairs = 0;
     int chunks = 0;
+    bool single = save && len0 >= M;  // saving with one chunk of every rank
     for (int c = 0;; ++c) {
+        if (single && c == 0) len = std::max<int64_t>(M, 1);
         len = std::min(len, M - r0);
         const bool last = r0 + len >= M;
         Chunk ch;
@@ -829,6 +840,26 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
             blend_ran = true;
         }
         if (last) break;
+        if (save && !single) {
+            // after the first chunk: keep it if every subpixel saturated
+            void *h = nullptr;
+            CHK(pinned_get(ctx, sizeof(Totals), &h));
+            HIPCHK(ctx, hipMemcpyAsync(h, d_tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            if (((const Totals *)h)->alive == 0) break;
+            // not saturated: start again with one chunk of every rank
+            single = true;
+            CHK(reset_state());
+            bin.alive_sat = nullptr;
+            if (bp.work) HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 8, s));
+            ctx->stats.blend_launches = 0;
+            blend_ran = false;
+            pairs = 0;
+            chunks = 0;
+            r0 = 0;
+            c = -1;
+            continue;
+        }
         r0 += len;
         len *= 4;
     }

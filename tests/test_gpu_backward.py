@@ -131,6 +131,38 @@ def test_saving_does_not_change_the_image(lib):
     d.close()
 
 
+@pytest.mark.parametrize("first_chunk", [1, 8])
+def test_saved_lists_do_not_depend_on_the_chunk_schedule(lib, first_chunk):
+    """A render that keeps its lists for the backward keeps its first depth
+    chunk only when every subpixel saturated there, else it renders again with
+    one chunk of every rank.  In this scene (background showing through, so
+    not everything saturates early) a small first chunk takes the second
+    route; images and gradients must equal those of the one-chunk render."""
+    lfr, ctx = lib
+    scene = _branchy_scene()
+    params, cams, V = _branchy_setup(2)
+    params = params.with_tile(8, 8)
+    n = 3 * params.width * params.height
+    gout = np.random.Generator(np.random.PCG64(31)).standard_normal(n).astype(np.float32)
+    g = torch.from_numpy(gout.reshape(params.height, params.width, 3)).to("cuda:0")
+    say("saved lists, first chunk", first_chunk)
+    d = lfr.Display(ctx, params)
+    ds = lfr.DeviceScene.from_numpy(scene, device="cuda:0")
+    res = []
+    for fc in (0, first_chunk):
+        img = lfr.render(ctx, d, ds, cams, cluster_size=2, background=(0.2, 0.1, 0.3), save_for_backward=True,
+                         first_chunk=fc).clone()
+        grads = {k: v.clone() for k, v in lfr.render_backward(ctx, d, ds, g).items()}
+        torch.cuda.synchronize()
+        res.append((img, grads, ctx.stats()["chunks"]))
+    assert res[0][2] == 1 and res[1][2] == 1
+    assert torch.equal(res[0][0], res[1][0])
+    for k in NAMES:
+        a, b = res[0][1][k].double(), res[1][1][k].double()
+        assert torch.linalg.norm(a - b) <= 1e-5 * torch.linalg.norm(a) + 1e-30, k
+    d.close()
+
+
 def test_autograd_function_mse(lib):
     lfr, ctx = lib
     scene, params, cams_list = grad_subset()
