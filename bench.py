@@ -305,8 +305,8 @@ def cpu_baseline(w, scene, cams, n_samples):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it would "
-              "shard); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; rerun with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

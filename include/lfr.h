@@ -49,7 +49,7 @@ typedef int32_t lfr_status;
 #define LFR_ERR_OUT_OF_MEMORY (-2)/* device allocation failed                 */
 #define LFR_ERR_HIP         (-3)  /* a HIP runtime call or launch failed      */
 #define LFR_ERR_CAPACITY    (-4)  /* workspace limit set by the caller exceeded */
-#define LFR_ERR_UNSUPPORTED (-5)  /* valid but outside what this build handles */
+#define LFR_ERR_UNSUPPORTED (-5)  /* valid but outside what the library handles */
 
 typedef struct lfr_context lfr_context;  /* device, stream, workspace, stats, last error */
 typedef struct lfr_display lfr_display;  /* view map V, remap LUT Psi, per-tile tables  */
