@@ -289,13 +289,13 @@ ViewTables build_tables(const lfr_display *d, int S, bool cull)
 // Device copy of the small per-render tables, laid out in one buffer.
 struct DevTables {
     DevCamera *cams = nullptr;
-    int32_t *cluster_cam = nullptr, *view_cam = nullptr, *cv_off = nullptr, *cv_list = nullptr,
+    int32_t *cluster_cam = nullptr, *view_cam = nullptr, *cv_off = nullptr, *cv_list = nullptr, *cv_cam = nullptr,
             *view_slot = nullptr, *view_cluster = nullptr;
 };
 
 size_t tables_bytes(const lfr_display *d, const ViewTables &vt)
 {
-    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + vt.cv_list.size() + 2 * d->N;
+    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + 2 * vt.cv_list.size() + 2 * d->N;
     return sizeof(DevCamera) * d->N + n_int * sizeof(int32_t);
 }
 
@@ -319,6 +319,9 @@ void write_tables(const lfr_display *d, const lfr_camera *cams, const ViewTables
     put(vt.view_ids, &out->view_cam);
     put(vt.cv_off, &out->cv_off);
     put(vt.cv_list, &out->cv_list);
+    std::vector<int32_t> cv_cam(vt.cv_list.size());
+    for (size_t e = 0; e < cv_cam.size(); ++e) cv_cam[e] = vt.view_ids[vt.cv_list[e]];
+    put(cv_cam, &out->cv_cam);
     put(vt.view_slot, &out->view_slot);
     put(vt.view_cluster, &out->view_cluster);
     out->cams = (DevCamera *)dv;
@@ -351,12 +354,16 @@ struct Projected {
 };
 
 // A tile grid over the W x H panel.
+// (tile sides are powers of two, checked where displays and full-frame
+// renders are set up, so a tile index is a shift of a pixel index)
 struct Grid {
     int W, H, tw, th, TX, TY, T;
+    int tw_shift, th_shift;
 };
 Grid make_grid(int W, int H, int tw, int th)
 {
-    Grid g{W, H, tw, th, (W + tw - 1) / tw, (H + th - 1) / th, 0};
+    Grid g{W, H, tw, th, (W + tw - 1) / tw, (H + th - 1) / th, 0, __builtin_ctz((unsigned)tw),
+           __builtin_ctz((unsigned)th)};
     g.T = g.TX * g.TY;
     return g;
 }
@@ -396,8 +403,8 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MKp), &sort_temp));
     const size_t e0 = tm.mark(s);
-    const TileGrid tg{d->W, d->H, d->tw, d->th, dt.cv_off, dt.cv_list};
-    HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, tg, KC, dt.cluster_cam, NV, dt.view_cam, po, s));
+    const TileGrid tg{d->W, d->H, d->tw_shift, d->th_shift, dt.cv_off, dt.cv_list, dt.cv_cam};
+    HIPCHK(ctx, launch_project(scene_dev(scene), dt.cams, tg, KC, dt.cluster_cam, po, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStProject, e0, e1);
     bool alt = false;
@@ -425,7 +432,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.n_clusters = vt.n_clusters;
     bp.W = d->W;
     bp.H = d->H;
-    bp.tw = d->tw;
+    bp.tw_shift = d->tw_shift;
     bp.th = d->th;
     bp.TX = d->TX;
     bp.TY = d->TY;

@@ -75,8 +75,10 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &
 {
     const int w0 = (int)r.bbox.x >> 5;
     const int nw = ((int)r.bbox.y >> 5) - w0 + 1;
-    ty = (int)r.bbox.z + u / nw;
-    w = w0 + u % nw;
+    // (most items span one or two words: no integer division for those)
+    const int uq = nw == 1 ? u : (nw == 2 ? u >> 1 : u / nw);
+    ty = (int)r.bbox.z + uq;
+    w = w0 + (u - uq * nw);
     const int xb = w << 5;
     auto bits = [&](int lo, int hi) -> uint32_t {  // tiles [lo, hi] within the word
         lo -= xb;
@@ -93,7 +95,7 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &
         const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
         for (int v = 0; v < (int)r.nv; ++v) {
             int c0, c1;
-            if (row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 / bp.tw, c1 / bp.tw);
+            if (row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
         }
     }
     const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;

@@ -78,7 +78,6 @@ struct ViewTables {
     std::vector<int32_t> view_ids;        // [N'] original view id per slot
     std::vector<int32_t> view_slot;       // [N] slot of view j (-1 if none)
     std::vector<int32_t> view_cluster;    // [N] compact cluster of view j (-1 if none)
-    std::vector<int32_t> cam_index;       // [K'+N'] camera per projected slot
 };
 
 // Per (display, cluster size, culling): blend work items and the number of
@@ -200,13 +199,14 @@ struct ProjectOut {
     int64_t Mp;         // M rounded up to the sort's segment granule
 };
 struct TileGrid {
-    int W, H, tw, th;
+    int W, H;
+    int tw_shift, th_shift;  // tile side = 1 << shift pixels
     const int32_t *cv_off;   // [K'+1] views of each cluster ...
     const int32_t *cv_list;  // ... as view slots
+    const int32_t *cv_cam;   // camera (view id) of each cv_list entry
 };
 hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileGrid &tg,
-                          int n_clusters, const int32_t *cluster_cam, int n_views,
-                          const int32_t *view_cam, const ProjectOut &out, hipStream_t s);
+                          int n_clusters, const int32_t *cluster_cam, const ProjectOut &out, hipStream_t s);
 hipError_t launch_project_records(const SceneDev &sc, const DevCamera *cam, int W, int H,
                                   lfr_proj_record *out, hipStream_t s);
 
@@ -236,7 +236,7 @@ struct BinParams {
     int64_t M;
     int64_t Mp;               // stride of the per-cluster depth-sorted arrays
     int n_clusters;
-    int W, H, tw, th, TX, TY;
+    int W, H, tw_shift, th, TX, TY;  // tile width = 1 << tw_shift pixels
     int cluster_bits;
     const int32_t *cv_off;    // [K'+1]
     const int32_t *cv_list;   // compact view slots

@@ -6,11 +6,13 @@
 // Layout: one thread per Gaussian.  A block first copies its Gaussians' SH
 // coefficients into LDS with coalesced loads (rows of odd pitch, so the
 // per-thread reads that follow are free of bank conflicts); each thread
-// then builds the 3D covariance once and loops over the projected views
-// (means) and clusters (full records), writing each output plane [slot][M]
-// coalesced across the wavefront.  A (cluster, Gaussian) whose boxes miss
-// the panel in every view of the cluster gets the "invalid" depth key and no
-// record: it sorts last and is never binned.
+// then builds the 3D covariance once and loops over the clusters: the full
+// record at the representative view, then the mean in each projected view
+// of the cluster (every projected view belongs to exactly one cluster), whose
+// tile boxes are unioned while the mean is still in registers.  Each output
+// plane [slot][M] is written coalesced across the wavefront.  A (cluster,
+// Gaussian) whose boxes miss the panel in every view of the cluster gets the
+// "invalid" depth key and no record: it sorts last and is never binned.
 //
 // Arithmetic is IEEE double with FMA contraction disabled (the library is
 // built with -ffp-contract=off); results are rounded to float32 once, when
@@ -252,8 +254,8 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
     const float fy0 = fmaxf(ceilf(m.y - e.y - 0.5f), 0.0f);
     const float fy1 = fminf(floorf(m.y + e.y - 0.5f), (float)(tg.H - 1));
     if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
-    b = make_ushort4((unsigned short)((int)fx0 / tg.tw), (unsigned short)((int)fx1 / tg.tw),
-                     (unsigned short)((int)fy0 / tg.th), (unsigned short)((int)fy1 / tg.th));
+    b = make_ushort4((unsigned short)((int)fx0 >> tg.tw_shift), (unsigned short)((int)fx1 >> tg.tw_shift),
+                     (unsigned short)((int)fy0 >> tg.th_shift), (unsigned short)((int)fy1 >> tg.th_shift));
     return true;
 }
 
@@ -262,7 +264,6 @@ constexpr int kProjBlock = 256;
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
                                                       int n_clusters, const int32_t *__restrict__ cluster_cam,
-                                                      int n_views, const int32_t *__restrict__ view_cam,
                                                       ProjectOut out)
 {
     constexpr int NS = (DEG + 1) * (DEG + 1) * 3;  // SH floats per Gaussian
@@ -294,12 +295,6 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     load_gaussian<DEG>(sc, i, g, shc, false);
     const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
     const float nanf_ = __builtin_nanf("");
-
-    for (int v = 0; v < n_views; ++v) {
-        const DevCamera &c = cams[view_cam[v]];
-        const MeanProj m = project_mean(c, mx, my, mz, g.finite);
-        out.mean2d[(int64_t)v * M + i] = m.valid ? m.m2d : make_float2(nanf_, nanf_);
-    }
     const bool want_cov = g.finite && g.o >= kAlphaMin;
     Cov3 S = {};
     if (want_cov) S = cov3d(g.ls, g.q);
@@ -311,52 +306,50 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
+        // the cluster's views: mean planes, and the union of the tile boxes
+        // of this Gaussian's mean in each view with the cluster's extents
+        // (means placed by selects, not by a dynamic index, so that the
+        // record stays in registers)
+        float2 mv[kItemViews];
+#pragma unroll
+        for (int q = 0; q < kItemViews; ++q) mv[q] = make_float2(0.f, 0.f);
+        int nv = 0;
+        unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
+        for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
+            const MeanProj mj = project_mean(cams[tg.cv_cam[v]], mx, my, mz, g.finite);
+            const float2 m2 = mj.valid ? mj.m2d : make_float2(nanf_, nanf_);
+            out.mean2d[(int64_t)tg.cv_list[v] * M + i] = m2;
+            ushort4 b;
+            if (!f.valid || !mj.valid || !tile_box(m2, f.ext, tg, b)) continue;
+#pragma unroll
+            for (int q = 0; q < kItemViews; ++q)
+                if (q == nv) mv[q] = m2;
+            ++nv;
+            x0 = min(x0, b.x);
+            x1 = max(x1, b.y);
+            y0 = min(y0, b.z);
+            y1 = max(y1, b.w);
+        }
         bool binned = false;
-        if (f.valid) {
-            // tile boxes of the cluster's views: this Gaussian's mean in each
-            // view (the same values the per-view mean planes hold) with the
-            // cluster's extents
-            // (means placed by selects, not by a dynamic index, so that the
-            // record stays in registers)
-            float2 mv[kItemViews];
+        if (nv != 0) {
+            ItemRec it;
+            it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
+            it.flags = nv > kItemViews ? 1 : 0;
+            it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
+            it.bbox = make_ushort4(x0, x1, y0, y1);
+            it.a = f.conic[0];
+            it.beta = f.conic[1];
+            it.g = f.conic[2];
+            it.pad = 0.0f;
 #pragma unroll
-            for (int q = 0; q < kItemViews; ++q) mv[q] = make_float2(0.f, 0.f);
-            int nv = 0;
-            unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
-            for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
-                // this thread wrote the view's mean above (NaN if invalid)
-                const float2 m2 = out.mean2d[(int64_t)tg.cv_list[v] * M + i];
-                ushort4 b;
-                if (isnan(m2.x) || !tile_box(m2, f.ext, tg, b)) continue;
-#pragma unroll
-                for (int q = 0; q < kItemViews; ++q)
-                    if (q == nv) mv[q] = m2;
-                ++nv;
-                x0 = min(x0, b.x);
-                x1 = max(x1, b.y);
-                y0 = min(y0, b.z);
-                y1 = max(y1, b.w);
-            }
-            if (nv != 0) {
-                ItemRec it;
-                it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
-                it.flags = nv > kItemViews ? 1 : 0;
-                it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
-                it.bbox = make_ushort4(x0, x1, y0, y1);
-                it.a = f.conic[0];
-                it.beta = f.conic[1];
-                it.g = f.conic[2];
-                it.pad = 0.0f;
-#pragma unroll
-                for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
-                out.items[idx] = it;
-                out.ibox[idx] = it.bbox;
-                GaussRec r;
-                r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
-                r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
-                out.rec[idx] = r;
-                binned = true;
-            }
+            for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
+            out.items[idx] = it;
+            out.ibox[idx] = it.bbox;
+            GaussRec r;
+            r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
+            r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
+            out.rec[idx] = r;
+            binned = true;
         }
         out.dkey[kidx] = binned ? __float_as_uint(m.depth) : 0xFFFFFFFFu;
     }
@@ -398,17 +391,16 @@ __global__ void __launch_bounds__(256) project_records_kernel(SceneDev sc, const
 }
 
 hipError_t launch_project(const SceneDev &sc, const DevCamera *cams, const TileGrid &tg, int n_clusters,
-                          const int32_t *cluster_cam, int n_views, const int32_t *view_cam,
-                          const ProjectOut &out, hipStream_t s)
+                          const int32_t *cluster_cam, const ProjectOut &out, hipStream_t s)
 {
     const int64_t n = sc.M > out.Mp ? sc.M : out.Mp;
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kProjBlock - 1) / kProjBlock)), block(kProjBlock);
     switch (sc.deg) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
-    default: hipLaunchKernelGGL(project_kernel<3>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, n_views, view_cam, out); break;
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, out); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, out); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, out); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, block, 0, s, sc, cams, tg, n_clusters, cluster_cam, out); break;
     }
     return hipGetLastError();
 }
