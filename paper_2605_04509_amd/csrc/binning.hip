@@ -102,6 +102,20 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &
     return m & alive_k[(int64_t)ty * bp.alive_words + w];
 }
 
+// The record of lane `owner`, handed over through lane exchanges (the lanes
+// that work on an item's units read it from the lane that loaded it, not
+// from memory).
+__device__ __forceinline__ ItemRec shfl_item(const ItemRec &own, int owner)
+{
+    uint32_t w[16];
+    __builtin_memcpy(w, &own, sizeof(ItemRec));
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = (uint32_t)__shfl((int)w[k], owner, 64);
+    ItemRec r;
+    __builtin_memcpy(&r, w, sizeof(ItemRec));
+    return r;
+}
+
 // Position of the k-th set bit of m (k < popcount(m)).
 __device__ inline int select_bit(uint32_t m, int k)
 {
@@ -171,6 +185,7 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     const ItemRec *items_k = bp.items + (int64_t)k * bp.M;
     uint32_t i = 0;
     int U = 0;
+    ItemRec own = {};  // this lane's item record (when it has units)
     // a cluster without any list that still has unsaturated subpixels emits
     // nothing (the summed-area table's total)
     const bool cluster_alive =
@@ -184,8 +199,10 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
             // items whose tiles are all saturated emit nothing: the counting
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
-            if (kEmit || !bp.alive_sat || rect_alive(bp, k, bp.ibox[(int64_t)k * bp.M + i]))
-                U = item_units(items_k[i]);
+            if (kEmit || !bp.alive_sat || rect_alive(bp, k, bp.ibox[(int64_t)k * bp.M + i])) {
+                own = items_k[i];
+                U = item_units(own);
+            }
         }
     }
     const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);
@@ -202,7 +219,8 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         const uint32_t uloc = (has ? u : utot - 1) - (uint32_t)__shfl((int)ubase, owner, 64);
         int ty = 0, w = 0;
         uint32_t m = 0;
-        if (has) m = unit_mask(bp, k, items_k[iown], (int)uloc, ty, w);
+        const ItemRec rown = shfl_item(own, owner);
+        if (has) m = unit_mask(bp, k, rown, (int)uloc, ty, w);
         const uint32_t c = (uint32_t)__popc(m);
         if (!kEmit) {
             if (c) atomicAdd(&s_cnt[wave][owner], c);
