@@ -144,8 +144,7 @@ template <int DEG>
 __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, const Cov3 &S,
                                         double mx, double my, double mz, float o, const float *shc)
 {
-    FullProj f;
-    f.valid = false;
+    FullProj f = {};
     const double *R = c.R;
     // T1 = R Sigma (rows 0..2), Vc = T1 R^T (entries used below)
     const double s00 = S.xx, s01 = S.xy, s02 = S.xz, s11 = S.yy, s12 = S.yz, s22 = S.zz;
@@ -261,6 +260,34 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
 
 constexpr int kProjBlock = 256;
 
+// Store of the 64 lanes' records (Q pieces of 16 bytes each), consecutive in
+// memory from dst, as Q stores of 1 KB each: in store j, lane l writes piece
+// l % Q of record j * (64 / Q) + l / Q, fetched from that record's lane by lane
+// exchanges.  Each store then fills whole cache lines, where a per-lane
+// record store would write 16 bytes into each of 64 lines.
+template <int Q>
+__device__ __forceinline__ void wave_store(uint4 *dst, const uint4 (&pc)[Q], int lane)
+{
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const int src = j * (64 / Q) + lane / Q;
+        const int which = lane % Q;
+        uint32_t o[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint32_t v = 0u;
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const uint32_t w = t == 0 ? pc[p].x : (t == 1 ? pc[p].y : (t == 2 ? pc[p].z : pc[p].w));
+                const uint32_t got = (uint32_t)__shfl((int)w, src, 64);
+                v = which == p ? got : v;
+            }
+            o[t] = v;
+        }
+        dst[j * 64 + lane] = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const DevCamera *__restrict__ cams, TileGrid tg,
                                                       int n_clusters, const int32_t *__restrict__ cluster_cam,
@@ -295,14 +322,18 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     load_gaussian<DEG>(sc, i, g, shc, false);
     const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
     const float nanf_ = __builtin_nanf("");
+    // all 64 Gaussians of this wavefront exist: its records are written with
+    // whole-wavefront stores (also those of pairs that are not binned, which
+    // nothing reads)
+    const int lane = threadIdx.x & 63;
+    const bool full_wave = i - lane + 64 <= M;
     const bool want_cov = g.finite && g.o >= kAlphaMin;
     Cov3 S = {};
     if (want_cov) S = cov3d(g.ls, g.q);
     for (int k = 0; k < n_clusters; ++k) {
         const DevCamera &c = cams[cluster_cam[k]];
         const MeanProj m = project_mean(c, mx, my, mz, g.finite);
-        FullProj f;
-        f.valid = false;
+        FullProj f = {};
         if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
@@ -330,26 +361,32 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
             y0 = min(y0, b.z);
             y1 = max(y1, b.w);
         }
-        bool binned = false;
-        if (nv != 0) {
-            ItemRec it;
-            it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
-            it.flags = nv > kItemViews ? 1 : 0;
-            it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
-            it.bbox = make_ushort4(x0, x1, y0, y1);
-            it.a = f.conic[0];
-            it.beta = f.conic[1];
-            it.g = f.conic[2];
-            it.pad = 0.0f;
+        const bool binned = nv != 0;
+        ItemRec it;
+        it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
+        it.flags = nv > kItemViews ? 1 : 0;
+        it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
+        it.bbox = make_ushort4(x0, x1, y0, y1);
+        it.a = f.conic[0];
+        it.beta = f.conic[1];
+        it.g = f.conic[2];
+        it.pad = 0.0f;
 #pragma unroll
-            for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
+        for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
+        GaussRec r;
+        r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
+        r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
+        if (full_wave) {
+            uint4 ip[4], rp[2];
+            __builtin_memcpy(ip, &it, sizeof(ItemRec));
+            __builtin_memcpy(rp, &r, sizeof(GaussRec));
+            wave_store<4>(reinterpret_cast<uint4 *>(out.items + (idx - lane)), ip, lane);
+            wave_store<2>(reinterpret_cast<uint4 *>(out.rec + (idx - lane)), rp, lane);
+            out.ibox[idx] = it.bbox;
+        } else if (binned) {
             out.items[idx] = it;
             out.ibox[idx] = it.bbox;
-            GaussRec r;
-            r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
-            r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
             out.rec[idx] = r;
-            binned = true;
         }
         out.dkey[kidx] = binned ? __float_as_uint(m.depth) : 0xFFFFFFFFu;
     }
