@@ -13,14 +13,14 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kSortWaves = kSortBlock / 64;
 
-// Histogram layout: [digit][tile] for one segment; with segments of seg
-// tiles each (seg > 0), [segment][digit][tile in segment], so that one
-// linear exclusive scan keeps every segment's keys inside the segment (a
-// segmented sort: keys never cross segment boundaries).
-__device__ __forceinline__ int64_t hist_index(int d, int64_t tile, int64_t nb, int64_t seg)
+// Histogram layout (nd = digit values of the pass): [digit][tile] for one
+// segment; with segments of seg tiles each (seg > 0), [segment][digit][tile in
+// segment], so that one linear exclusive scan keeps every segment's keys
+// inside the segment (a segmented sort: keys never cross segment boundaries).
+__device__ __forceinline__ int64_t hist_index(int d, int64_t tile, int64_t nb, int64_t seg, int nd)
 {
     if (seg == 0) return (int64_t)d * nb + tile;
-    return ((tile / seg) * 256 + d) * seg + tile % seg;
+    return ((tile / seg) * nd + d) * seg + tile % seg;
 }
 
 // The element count is n, or min(*dn, n) when dn is given (a count known only
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
         if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[hist_index(threadIdx.x, blockIdx.x, nb, seg)] = h[threadIdx.x];
+    if (threadIdx.x <= mask) hist[hist_index(threadIdx.x, blockIdx.x, nb, seg, (int)mask + 1)] = h[threadIdx.x];
 }
 
 // Scatter of one 4096-key tile.  Wavefront w ranks the contiguous keys
@@ -82,8 +82,9 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
 
     // digit starts inside the tile: exclusive scan of this tile's histogram
     {
-        const int64_t hi = hist_index(tid, blockIdx.x, nb, seg);
-        const uint32_t h = hist[hi];
+        const bool dig = (uint32_t)tid <= mask;  // a digit value of this pass
+        const int64_t hi = dig ? hist_index(tid, blockIdx.x, nb, seg, (int)mask + 1) : 0;
+        const uint32_t h = dig ? hist[hi] : 0u;
         uint32_t incl = h;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
             if (lane >= d) incl += t;
         }
         if (lane == 63) s_wsum[wave] = incl;
-        s_gbase[tid] = offs[hi];
+        s_gbase[tid] = dig ? offs[hi] : 0u;
 #pragma unroll
         for (int w = 0; w < kSortWaves; ++w) s_cnt[w][tid] = 0;
         __syncthreads();
@@ -174,18 +175,23 @@ static hipError_t radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int6
     *in_alt = false;
     if (n <= 1 || b1 <= b0) return hipSuccess;
     const int64_t nb = sort_tiles(n);
-    const int64_t nh = 256 * nb;
+    const int64_t nh = 256 * nb;  // room for 8-bit digits; a pass with fewer uses its first part
     uint32_t *hist = (uint32_t *)temp;
     uint32_t *offs = hist + nh;
     void *stemp = (void *)(((uintptr_t)(offs + nh) + 63) & ~(uintptr_t)63);
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
-    for (int shift = b0; shift < b1; shift += 8) {
-        const int bits = (b1 - shift) < 8 ? (b1 - shift) : 8;
+    // as few passes of at most 8 bits as the range needs, the bits spread
+    // evenly over them (fewer digit values per pass give longer runs of
+    // consecutive output slots in the scatter)
+    const int passes = (b1 - b0 + 7) / 8;
+    const int step = (b1 - b0 + passes - 1) / passes;
+    for (int shift = b0; shift < b1; shift += step) {
+        const int bits = (b1 - shift) < step ? (b1 - shift) : step;
         const uint32_t mask = (1u << bits) - 1u;
         hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, n, dn, shift,
                            mask, hist, nb, seg);
-        hipError_t e = launch_exclusive_scan(hist, offs, nh, stemp, nullptr, s);
+        hipError_t e = launch_exclusive_scan(hist, offs, (int64_t)(mask + 1) * nb, stemp, nullptr, s);
         if (e != hipSuccess) return e;
         const size_t ea = tm ? tm->mark(s) : 0;
         hipLaunchKernelGGL(sort_scatter_kernel<K>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, ki, vi, ko, vo, n,
