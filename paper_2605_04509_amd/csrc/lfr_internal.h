@@ -215,8 +215,9 @@ size_t scan_temp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, void *temp,
                                  uint64_t *total, hipStream_t s);
 
-// Stable LSD radix sort on bits [b0, b1) with 8-bit digits; ping-pong
-// between (k0, v0) and (k1, v1).  Returns in *result_in_alt whether the
+// Stable LSD radix sort on bits [b0, b1) in ceil((b1 - b0) / 8) passes of at
+// most 8 bits each, the bits spread evenly; ping-pong between (k0, v0) and
+// (k1, v1).  Returns in *result_in_alt whether the
 // sorted data ended in (k1, v1).
 size_t sort_temp_bytes(int64_t n);
 // With a timer, every scatter launch is recorded as a kStScatter span.  With

@@ -1,4 +1,4 @@
-// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+// Stable LSD radix sort of (key, value) pairs, digits of at most 8 bits.
 //
 // Per pass: (1) every 4096-key tile builds a 256-bin digit histogram in LDS;
 // (2) the [digit][tile] histogram matrix is exclusive-scanned, giving every
