@@ -1,8 +1,10 @@
 """CPU oracle for the subpixel-level light-field Gaussian rasterizer.
 
-TEST INFRASTRUCTURE ONLY.  A plain, slow, single-threaded C implementation
-(``lfr_oracle.c``) of what the method computes, written from the paper, plus
-this ctypes wrapper.  It shares no code with the HIP library.  Only the test
+TEST INFRASTRUCTURE ONLY.  A plain, slow C implementation (``lfr_oracle.c``)
+of what the method computes, written from the paper, plus this ctypes
+wrapper.  It is single-threaded unless :func:`set_threads` asks for more;
+its parallel loops split independent items, so results are bit-identical for
+any thread count.  It shares no code with the HIP library.  Only the test
 suite, the smoke check and the benchmark's CPU-baseline leg may import it.
 
 Functions and the passages they follow:
@@ -12,6 +14,8 @@ Functions and the passages they follow:
 * :func:`remap`           -- section 4.3, Eq. 8
 * :func:`project`         -- section 4.1 Eq. 4; section 4.2 Eq. 5-6
 * :func:`render_subpixels`-- section 4.3 Eq. 9-10 with the reuse rule of 4.2
+* :func:`render_subpixels_ranged` -- the same, plus the range of values a
+  float32 renderer may reach when near-threshold decisions go either way
 * :func:`render_view`     -- section 3.3 (standard full-frame blend)
 * :func:`render_interlaced_fullframe` -- render every view, then sample the
   subpixel each view owns (the full-frame-then-interlace definition)
@@ -49,7 +53,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _DEPS):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
+                               "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm", "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -74,6 +78,13 @@ def _load():
             lib.orc_render_subpixels.argtypes = [i64, i32, P, P, P, P, P, P, i32, P, i32, i32, i32,
                                                  P, i64, P, P, P, P]
             lib.orc_render_subpixels.restype = ctypes.c_int
+            lib.orc_render_subpixels_ex.argtypes = [i64, i32, P, P, P, P, P, P, i32, P, i32, i32, i32,
+                                                    P, i64, P, P, P, P, P, P, P]
+            lib.orc_render_subpixels_ex.restype = ctypes.c_int
+            lib.orc_set_threads.argtypes = [i32]
+            lib.orc_set_threads.restype = None
+            lib.orc_get_threads.argtypes = []
+            lib.orc_get_threads.restype = i32
             lib.orc_render_view.argtypes = [i64, i32, P, P, P, P, P, P, i32, i32, P, P, P, P]
             lib.orc_render_view.restype = None
             lib.orc_grad_subpixels.argtypes = [i64, i32, P, P, P, P, P, P, i32, P, i32, i32, i32, P,
@@ -165,6 +176,74 @@ def render_subpixels(scene, cams_packed, display, V, cluster_size, samples, bg=(
     return out, flags, tflag
 
 
+def render_subpixels_ranged(scene, cams_packed, display, V, cluster_size, samples, bg=(0.0, 0.0, 0.0)):
+    """:func:`render_subpixels` plus the admissible range of every sample.
+
+    Returns a dict with ``out``, ``flags``, ``tflag`` (as render_subpixels),
+    ``lo`` / ``hi`` (float32: the smallest and largest value over every way
+    the flagged near-threshold decisions can go; equal to ``out`` when
+    nothing is flagged) and ``paths`` (leaves explored; negative when the
+    64-leaf limit cut some branch off, in which case the range is
+    incomplete)."""
+    arrs, ptrs = _scene_args(scene)
+    cams = _f32(cams_packed).reshape(-1, 16)
+    V = np.ascontiguousarray(V, dtype=np.int32)
+    samples = np.ascontiguousarray(samples, dtype=np.int64)
+    bgv = _f32(bg)
+    n = samples.shape[0]
+    r = {"out": np.empty(n, np.float32), "flags": np.empty(n, np.int32), "tflag": np.empty(n, np.float64),
+         "lo": np.empty(n, np.float32), "hi": np.empty(n, np.float32), "paths": np.empty(n, np.int32)}
+    rc = _load().orc_render_subpixels_ex(scene.num_gaussians, scene.sh_degree, *ptrs, _ptr(cams),
+                                         cams.shape[0], _ptr(V), display.width, display.height,
+                                         cluster_size, _ptr(bgv), n, _ptr(samples),
+                                         *[_ptr(r[k]) for k in ("out", "flags", "tflag", "lo", "hi", "paths")])
+    if rc != 0:
+        raise ValueError("invalid render arguments")
+    return r
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the oracle's parallel loops; returns the previous count."""
+    lib = _load()
+    prev = lib.orc_get_threads()
+    lib.orc_set_threads(int(n))
+    return prev
+
+
+def get_threads() -> int:
+    return _load().orc_get_threads()
+
+
+def host_threads() -> int:
+    """The host threads a run may use: OMP_NUM_THREADS when set (the GPU
+    hosts set it to the CPU share of one GPU), else the visible cores, at
+    most 16."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+class threads:
+    """Context manager: run the oracle on n host threads inside the block."""
+
+    def __init__(self, n: int | None = None):
+        self.n = host_threads() if n is None else n
+        self.prev = None
+
+    def __enter__(self):
+        self.prev = set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
+
+
 def render_frame(scene, cams_packed, display, V, cluster_size, bg=(0.0, 0.0, 0.0)):
     """Every subpixel of the panel, as an [H, W, 3] image (plus flags, tflag)."""
     n = 3 * display.width * display.height
@@ -172,6 +251,15 @@ def render_frame(scene, cams_packed, display, V, cluster_size, bg=(0.0, 0.0, 0.0
                                          np.arange(n, dtype=np.int64), bg)
     shp = (display.height, display.width, 3)
     return out.reshape(shp), flags.reshape(shp), tflag.reshape(shp)
+
+
+def render_frame_ranged(scene, cams_packed, display, V, cluster_size, bg=(0.0, 0.0, 0.0)):
+    """:func:`render_subpixels_ranged` over every subpixel; each entry of the
+    returned dict has shape [H, W, 3]."""
+    n = 3 * display.width * display.height
+    r = render_subpixels_ranged(scene, cams_packed, display, V, cluster_size, np.arange(n, dtype=np.int64), bg)
+    shp = (display.height, display.width, 3)
+    return {k: v.reshape(shp) for k, v in r.items()}
 
 
 def render_view(scene, cam_packed, width, height, bg=(0.0, 0.0, 0.0)):

@@ -2,11 +2,12 @@
  * lfr_oracle.c -- CPU oracle for subpixel-level 3D Gaussian rasterization of
  * one interlaced light-field image (CoherentRaster, arXiv 2605.04509).
  *
- * TEST INFRASTRUCTURE ONLY: a plain, slow, single-threaded reference written
- * from the paper.  It shares no code with the HIP library; only the tests,
+ * TEST INFRASTRUCTURE ONLY: a plain, slow reference written from the paper
+ * (single-threaded unless orc_set_threads asks for more; the results are
+ * bit-identical for any thread count).  It shares no code with the HIP library; only the tests,
  * the smoke check and the benchmark's CPU-baseline leg may load it.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared lfr_oracle.c -lm
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared lfr_oracle.c -lm -lpthread
  *
  * What each function follows:
  *   orc_view_map         section 3.1, Eq. 1-3 (lenticular view-index map)
@@ -25,6 +26,7 @@
 #include "lfr_oracle_impl.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -294,16 +296,78 @@ static void project_one(const float *mu, const float *ls, const float *q, float 
     out->valid = ok;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Host threads.  Every parallel loop below splits independent items (one   */
+/* Gaussian, one subpixel, one image row) over threads; each item is         */
+/* computed by exactly the same operations as in a single-threaded run, so   */
+/* the results are bit-identical for any thread count.                      */
+/* ------------------------------------------------------------------------ */
+
+static int orc_threads = 1;
+
+void orc_set_threads(int32_t n) { orc_threads = n < 1 ? 1 : (n > 256 ? 256 : n); }
+int32_t orc_get_threads(void) { return orc_threads; }
+
+typedef void (*range_fn)(void *arg, int64_t begin, int64_t end);
+typedef struct { range_fn fn; void *arg; int64_t begin, end; } range_job;
+
+static void *run_range(void *p)
+{
+    range_job *j = (range_job *)p;
+    j->fn(j->arg, j->begin, j->end);
+    return NULL;
+}
+
+/* fn(arg, b, e) over contiguous pieces of [0, n). */
+static void parallel_for(int64_t n, int64_t min_per_thread, range_fn fn, void *arg)
+{
+    int64_t nt = orc_threads;
+    if (min_per_thread < 1) min_per_thread = 1;
+    if (nt > n / min_per_thread) nt = n / min_per_thread;
+    if (nt <= 1) {
+        if (n > 0) fn(arg, 0, n);
+        return;
+    }
+    pthread_t tid[256];
+    range_job job[256];
+    int started[256];
+    for (int64_t t = 0; t < nt; ++t) {
+        job[t].fn = fn;
+        job[t].arg = arg;
+        job[t].begin = n * t / nt;
+        job[t].end = n * (t + 1) / nt;
+        started[t] = t > 0 && pthread_create(&tid[t], NULL, run_range, &job[t]) == 0;
+    }
+    run_range(&job[0]);
+    for (int64_t t = 1; t < nt; ++t) {
+        if (started[t]) pthread_join(tid[t], NULL);
+        else run_range(&job[t]);      /* could not start a thread: do it here */
+    }
+}
+
+typedef struct {
+    int32_t deg, nb;
+    const float *means, *log_scales, *quats, *opac, *sh;
+    const orc_cam *c;
+    orc_proj *out;
+} project_job;
+
+static void project_range(void *p, int64_t b, int64_t e)
+{
+    const project_job *j = (const project_job *)p;
+    for (int64_t i = b; i < e; ++i)
+        project_one(j->means + 3 * i, j->log_scales + 3 * i, j->quats + 4 * i, j->opac[i],
+                    j->sh + (int64_t)j->nb * 3 * i, j->nb, j->deg, j->c, j->out + i);
+}
+
 void orc_project(int64_t M, int32_t deg, const float *means, const float *log_scales,
                  const float *quats, const float *opac, const float *sh, const float *cam,
                  int32_t W, int32_t H, orc_proj *out)
 {
     orc_cam c;
     orc_load_cam(cam, W, H, &c);
-    int32_t nb = (deg + 1) * (deg + 1);
-    for (int64_t i = 0; i < M; ++i)
-        project_one(means + 3 * i, log_scales + 3 * i, quats + 4 * i, opac[i],
-                    sh + (int64_t)nb * 3 * i, nb, deg, &c, out + i);
+    project_job j = {deg, (deg + 1) * (deg + 1), means, log_scales, quats, opac, sh, &c, out};
+    parallel_for(M, 4096, project_range, &j);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -336,68 +400,186 @@ static int64_t depth_order(int64_t M, const orc_proj *rep, int64_t *order)
     return n;
 }
 
-/* Blend the ordered list at sample position (px, py) for the channels in
- * [u0, u1).  Mean and validity come from `view`, the conic, colour and
- * opacity from `rep` (the same array on the exact path). */
-static void blend(double px, double py, int u0, int u1, const int64_t *order, int64_t n,
-                  const orc_proj *rep, const orc_proj *view, const float *bg, float *out,
-                  int32_t *flag_out, double *tflag_out)
+/* The walk over one ordered list at sample position (px, py) for the
+ * channels [u0, u1).  Mean and validity come from `view`, the conic, colour
+ * and opacity from `rep` (the same array on the exact path).
+ *
+ * Near-threshold decisions.  A float32 evaluation of the same formulas (dx,
+ * dy, w = dx + beta dy, A' w^2 + G' dy^2, exp2 within one ulp, the opacity
+ * product) has, to first order in the unit roundoff u, an error in E of at
+ * most u * SE and a relative error in alpha of at most ea = ln2 * u * SE + 3u;
+ * T carries the accumulated bound relT.  An alpha or T' within FLAG_SAFETY
+ * times its bound of its threshold may fall on the other side in float32.
+ * The main walk takes every decision on the float32-rounded value and
+ * records the first such event (flags bit 0: alpha near 1/255, bit 1: T' near
+ * 1e-4; tflag = T before it).  With `branch` set, the walk also follows the
+ * other outcome of every flagged decision (a depth-first tree of at most
+ * MAX_PATHS leaves) and keeps the range [lo, hi] of the values its leaves
+ * reach: every value a float32 renderer can legitimately produce, up to its
+ * own rounding of the sums. */
+#define MAX_PATHS 64
+
+typedef struct {
+    const int64_t *order;
+    int64_t n;
+    const orc_proj *rep, *view;
+    double px, py;
+    int u0, u1;
+    const float *bg;
+    int branch;
+    int paths, overflow;
+    double lo[3], hi[3];
+    float out[3];
+    int32_t flag;
+    double tflag;
+} walk_t;
+
+/* Continue the walk at list position e with state (T, C, relT).  At position
+ * fe the alpha-cutoff and stop decisions are forced to fcut / fstop when
+ * those are >= 0 (a branch taking the other outcome). */
+static void walk(walk_t *w, int64_t e, double T, const double *Cin, double relT,
+                 int64_t fe, int fcut, int fstop, int main_path)
 {
-    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-    int32_t flag = 0;
-    double tflag = 0.0;
-    double relT = 0.0;   /* bound on the relative error of a float32 T so far */
-    for (int64_t e = 0; e < n; ++e) {
-        int64_t i = order[e];
-        const orc_proj *g = rep + i, *m = view + i;
+    double C[3] = {Cin[0], Cin[1], Cin[2]};
+    for (; e < w->n; ++e) {
+        int64_t i = w->order[e];
+        const orc_proj *g = w->rep + i, *m = w->view + i;
         if (!m->valid_mean) continue;
-        double dx = px - (double)m->mean2d[0];
-        double dy = py - (double)m->mean2d[1];
+        double dx = w->px - (double)m->mean2d[0];
+        double dy = w->py - (double)m->mean2d[1];
         double beta = (double)g->conic[1];
-        double w = dx + beta * dy;
-        double E = (double)g->conic[0] * w * w + (double)g->conic[2] * dy * dy;
+        double ww = dx + beta * dy;
+        double E = (double)g->conic[0] * ww * ww + (double)g->conic[2] * dy * dy;
         double alpha = (double)g->opacity * exp2(-E);
         int clamped = alpha > ALPHA_MAX;
         if (clamped) alpha = ALPHA_MAX;
-        /* Near-threshold detection.  A float32 evaluation of the same
-         * formulas (dx, dy, w = dx + beta dy, A' w^2 + G' dy^2, exp2 within one
-         * ulp, the opacity product) has, to first order in the unit roundoff
-         * u, an error in E of at most u * SE and a relative error in alpha of
-         * at most ea = ln2 * u * SE + 3u; T carries the accumulated bound
-         * relT.  An alpha or T' within FLAG_SAFETY times its bound of a
-         * threshold may fall on the other side in float32: such subpixels are
-         * flagged. */
-        double SE = 2.0 * (double)g->conic[0] * fabs(w) * (fabs(dx) + fabs(beta * dy) + fabs(w))
-                  + (double)g->conic[0] * w * w + 4.0 * (double)g->conic[2] * dy * dy + E;
+        double SE = 2.0 * (double)g->conic[0] * fabs(ww) * (fabs(dx) + fabs(beta * dy) + fabs(ww))
+                  + (double)g->conic[0] * ww * ww + 4.0 * (double)g->conic[2] * dy * dy + E;
         double ea = clamped ? 1e-6 : 0.6931471805599453 * U32 * SE + 3.0 * U32;
-        if (fabs(alpha - 1.0 / 255.0) <= FLAG_SAFETY * ea * alpha) {
-            if (!flag) tflag = T;
-            flag |= 1;
+        int forced = e == fe;
+        int near_cut = fabs(alpha - 1.0 / 255.0) <= FLAG_SAFETY * ea * alpha;
+        if (near_cut && main_path && !w->flag) {
+            w->tflag = T;
+            w->flag |= 1;
+        } else if (near_cut && main_path) {
+            w->flag |= 1;
         }
-        if ((float)alpha < ALPHA_MIN) continue;
+        int pass = (float)alpha >= ALPHA_MIN;
+        if (forced && fcut >= 0) {
+            pass = fcut;
+        } else if (near_cut && w->branch) {
+            if (w->paths + 1 < MAX_PATHS) {
+                ++w->paths;
+                walk(w, e, T, C, relT, e, !pass, -1, 0);
+            } else {
+                w->overflow = 1;
+            }
+        }
+        if (!pass) continue;
         double Tn = T * (1.0 - alpha);
         double step = (clamped ? 1e-6 : alpha / (1.0 - alpha) * ea) + 2.0 * U32;
-        if (fabs(Tn - 1e-4) <= FLAG_SAFETY * (relT + step) * Tn) {
-            if (!flag) tflag = T;
-            flag |= 2;
+        int near_stop = fabs(Tn - 1e-4) <= FLAG_SAFETY * (relT + step) * Tn;
+        if (near_stop && main_path && !w->flag) {
+            w->tflag = T;
+            w->flag |= 2;
+        } else if (near_stop && main_path) {
+            w->flag |= 2;
         }
-        if ((float)Tn < T_STOP) break;
-        for (int u = u0; u < u1; ++u) C[u] = C[u] + (double)g->color[u] * alpha * T;
+        int stop = (float)Tn < T_STOP;
+        if (forced && fstop >= 0) {
+            stop = fstop;
+        } else if (near_stop && w->branch) {
+            if (w->paths + 1 < MAX_PATHS) {
+                ++w->paths;
+                walk(w, e, T, C, relT, e, pass, !stop, 0);
+            } else {
+                w->overflow = 1;
+            }
+        }
+        if (stop) break;
+        for (int u = w->u0; u < w->u1; ++u) C[u] = C[u] + (double)g->color[u] * alpha * T;
         T = Tn;
         relT += step;
     }
-    for (int u = u0; u < u1; ++u) out[u - u0] = (float)(C[u] + T * (double)bg[u]);
-    if (flag_out) *flag_out = flag;
-    if (tflag_out) *tflag_out = tflag;
+    for (int u = w->u0; u < w->u1; ++u) {
+        double v = (double)(float)(C[u] + T * (double)w->bg[u]);
+        if (v < w->lo[u]) w->lo[u] = v;
+        if (v > w->hi[u]) w->hi[u] = v;
+        if (main_path) w->out[u] = (float)(C[u] + T * (double)w->bg[u]);
+    }
 }
 
-int orc_render_subpixels(int64_t M, int32_t deg, const float *means, const float *log_scales,
-                         const float *quats, const float *opac, const float *sh,
-                         const float *cams, int32_t N, const int32_t *V, int32_t W, int32_t H,
-                         int32_t S, const float *bg, int64_t n_samples, const int64_t *samples,
-                         float *out, int32_t *flags, double *tflag)
+static void blend_walk(walk_t *w, double px, double py, int u0, int u1)
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    w->px = px;
+    w->py = py;
+    w->u0 = u0;
+    w->u1 = u1;
+    w->paths = 1;
+    w->overflow = 0;
+    w->flag = 0;
+    w->tflag = 0.0;
+    for (int u = 0; u < 3; ++u) {
+        w->lo[u] = INFINITY;
+        w->hi[u] = -INFINITY;
+        w->out[u] = 0.0f;
+    }
+    walk(w, 0, 1.0, zero, 0.0, -1, -1, -1, 1);
+}
+
+/* One view's samples of orc_render_subpixels_ex. */
+typedef struct {
+    const int64_t *order;
+    int64_t n;
+    const orc_proj *rep, *view;
+    const float *bg;
+    int32_t W;
+    const int64_t *samples;   /* all samples */
+    const int64_t *which;     /* indices into samples of this view's */
+    float *out;
+    int32_t *flags;
+    double *tflag;
+    float *lo, *hi;
+    int32_t *paths;
+} view_job;
+
+static void view_range(void *p, int64_t b, int64_t e)
+{
+    const view_job *j = (const view_job *)p;
+    walk_t w;
+    w.order = j->order;
+    w.n = j->n;
+    w.rep = j->rep;
+    w.view = j->view;
+    w.bg = j->bg;
+    w.branch = j->lo != NULL;
+    for (int64_t q = b; q < e; ++q) {
+        int64_t s = j->which[q];
+        int64_t p = j->samples[s];
+        int32_t u = (int32_t)(p % 3);
+        int64_t pix = p / 3;
+        blend_walk(&w, (double)(pix % j->W) + 0.5, (double)(pix / j->W) + 0.5, u, u + 1);
+        j->out[s] = w.out[u];
+        if (j->flags) j->flags[s] = w.flag;
+        if (j->tflag) j->tflag[s] = w.tflag;
+        if (j->lo) {
+            j->lo[s] = (float)w.lo[u];
+            j->hi[s] = (float)w.hi[u];
+            j->paths[s] = w.overflow ? -w.paths : w.paths;
+        }
+    }
+}
+
+int orc_render_subpixels_ex(int64_t M, int32_t deg, const float *means, const float *log_scales,
+                            const float *quats, const float *opac, const float *sh,
+                            const float *cams, int32_t N, const int32_t *V, int32_t W, int32_t H,
+                            int32_t S, const float *bg, int64_t n_samples, const int64_t *samples,
+                            float *out, int32_t *flags, double *tflag,
+                            float *lo, float *hi, int32_t *paths)
 {
     if (M < 0 || N <= 0 || S <= 0 || W <= 0 || H <= 0) return -1;
+    if ((lo != NULL) != (hi != NULL) || (lo != NULL) != (paths != NULL)) return -1;
     int64_t total = 3 * (int64_t)W * H;
     for (int64_t s = 0; s < n_samples; ++s)
         if (samples[s] < 0 || samples[s] >= total) return -1;
@@ -409,6 +591,7 @@ int orc_render_subpixels(int64_t M, int32_t deg, const float *means, const float
     orc_proj *prep = (orc_proj *)malloc(sizeof(orc_proj) * mm);
     orc_proj *pview = (orc_proj *)malloc(sizeof(orc_proj) * mm);
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * mm);
+    int64_t *which = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_samples > 0 ? n_samples : 1));
     char *need = (char *)malloc((size_t)N);
     for (int32_t k = 0; k < K; ++k) {
         /* any sample in this cluster? */
@@ -429,19 +612,56 @@ int orc_render_subpixels(int64_t M, int32_t deg, const float *means, const float
                 orc_project(M, deg, means, log_scales, quats, opac, sh, cams + 16 * (int64_t)j, W, H, pview);
                 pv = pview;
             }
-            for (int64_t s = 0; s < n_samples; ++s) {
-                int64_t p = samples[s];
-                if (V[p] != j) continue;
-                int32_t u = (int32_t)(p % 3);
-                int64_t pix = p / 3;
-                double px = (double)(pix % W) + 0.5, py = (double)(pix / W) + 0.5;
-                blend(px, py, u, u + 1, order, n, prep, pv, bg, out + s,
-                      flags ? flags + s : NULL, tflag ? tflag + s : NULL);
-            }
+            int64_t nw = 0;
+            for (int64_t s = 0; s < n_samples; ++s)
+                if (V[samples[s]] == j) which[nw++] = s;
+            view_job job = {order, n, prep, pv, bg, W, samples, which, out, flags, tflag, lo, hi, paths};
+            parallel_for(nw, 1, view_range, &job);
         }
     }
-    free(slots); free(rep); free(prep); free(pview); free(order); free(need);
+    free(slots); free(rep); free(prep); free(pview); free(order); free(which); free(need);
     return 0;
+}
+
+int orc_render_subpixels(int64_t M, int32_t deg, const float *means, const float *log_scales,
+                         const float *quats, const float *opac, const float *sh,
+                         const float *cams, int32_t N, const int32_t *V, int32_t W, int32_t H,
+                         int32_t S, const float *bg, int64_t n_samples, const int64_t *samples,
+                         float *out, int32_t *flags, double *tflag)
+{
+    return orc_render_subpixels_ex(M, deg, means, log_scales, quats, opac, sh, cams, N, V, W, H, S, bg,
+                                   n_samples, samples, out, flags, tflag, NULL, NULL, NULL);
+}
+
+typedef struct {
+    const int64_t *order;
+    int64_t n;
+    const orc_proj *pr;
+    const float *bg;
+    int32_t W;
+    float *img;
+    int32_t *flags;
+    double *tflag;
+} rows_job;
+
+static void rows_range(void *p, int64_t b, int64_t e)
+{
+    const rows_job *j = (const rows_job *)p;
+    walk_t w;
+    w.order = j->order;
+    w.n = j->n;
+    w.rep = j->pr;
+    w.view = j->pr;
+    w.bg = j->bg;
+    w.branch = 0;
+    for (int64_t y = b; y < e; ++y)
+        for (int32_t x = 0; x < j->W; ++x) {
+            int64_t pix = y * j->W + x;
+            blend_walk(&w, x + 0.5, (double)y + 0.5, 0, 3);
+            for (int u = 0; u < 3; ++u) j->img[3 * pix + u] = w.out[u];
+            if (j->flags) j->flags[pix] = w.flag;
+            if (j->tflag) j->tflag[pix] = w.tflag;
+        }
 }
 
 void orc_render_view(int64_t M, int32_t deg, const float *means, const float *log_scales,
@@ -454,12 +674,8 @@ void orc_render_view(int64_t M, int32_t deg, const float *means, const float *lo
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * mm);
     orc_project(M, deg, means, log_scales, quats, opac, sh, cam, W, H, pr);
     int64_t n = depth_order(M, pr, order);
-    for (int32_t y = 0; y < H; ++y)
-        for (int32_t x = 0; x < W; ++x) {
-            int64_t pix = (int64_t)y * W + x;
-            blend(x + 0.5, y + 0.5, 0, 3, order, n, pr, pr, bg, img + 3 * pix,
-                  flags ? flags + pix : NULL, tflag ? tflag + pix : NULL);
-        }
+    rows_job job = {order, n, pr, bg, W, img, flags, tflag};
+    parallel_for(H, 1, rows_range, &job);
     free(pr);
     free(order);
 }

@@ -2,8 +2,11 @@
  * lfr_oracle.h -- CPU oracle for subpixel-level 3D Gaussian rasterization of
  * one interlaced light-field image (CoherentRaster, arXiv 2605.04509).
  *
- * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded
- * reference written from the paper's equations.  It shares no code with the
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow reference written from
+ * the paper's equations.  It runs single-threaded unless orc_set_threads
+ * asks for more; its parallel loops split independent items (Gaussians,
+ * subpixels, rows), each computed by the same operations, so the results
+ * are bit-identical for any thread count.  It shares no code with the
  * HIP library.  Only the test suite, the smoke check and the benchmark's
  * CPU-baseline leg may load it; the product path never does.
  *
@@ -83,6 +86,27 @@ int orc_render_subpixels(int64_t M, int32_t sh_degree, const float *means,
                          int32_t W, int32_t H, int32_t S, const float *bg,
                          int64_t n_samples, const int64_t *samples,
                          float *out, int32_t *flags, double *tflag);
+
+/* orc_render_subpixels plus, per sample, the range of values reachable when
+ * every flagged decision may go either way: the walk follows both outcomes
+ * of each near-threshold alpha-cutoff or stop decision (at most 64 leaves)
+ * and returns lo/hi, the smallest and largest leaf value (lo == hi == out
+ * when nothing is flagged), and paths, the number of leaves (negated when
+ * the 64-leaf limit cut some branch off).  lo, hi, paths: all NULL or all
+ * non-NULL. */
+int orc_render_subpixels_ex(int64_t M, int32_t sh_degree, const float *means,
+                            const float *log_scales, const float *quats,
+                            const float *opacities, const float *sh,
+                            const float *cams, int32_t N, const int32_t *V,
+                            int32_t W, int32_t H, int32_t S, const float *bg,
+                            int64_t n_samples, const int64_t *samples,
+                            float *out, int32_t *flags, double *tflag,
+                            float *lo, float *hi, int32_t *paths);
+
+/* Host threads used by orc_project, orc_render_subpixels(_ex) and
+ * orc_render_view (1..256; 1 by default). */
+void orc_set_threads(int32_t n);
+int32_t orc_get_threads(void);
 
 /* Standard single-view 3DGS render of a full W x H RGB image (section 3.3),
  * with the same blend rule; img is [H][W][3].  flags/tflag per pixel as

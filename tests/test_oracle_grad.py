@@ -299,3 +299,62 @@ def test_decision_modes_agree_on_generic_scene():
     for k in oracle.GRAD_NAMES:
         rel = np.linalg.norm(g0[k] - g1[k]) / np.linalg.norm(g0[k])
         assert rel <= 1e-4, (k, rel)
+
+
+def test_mse_gradient_on_the_500_gaussian_subset_matches_central_differences():
+    """The differentiable configuration's loss on its finite-difference
+    subset: 500 Gaussians drawn like the 200k-Gaussian display scene (SH3),
+    64x36 panel, 45 views over 40 degrees, exact path; L = mean over the
+    subpixels of (I - I*)^2 with I* rendered from the same scene with means +
+    N(0, 0.01).  Central differences of L itself (double forward, decisions
+    on the double values) at 16 sampled parameters of every group."""
+    from workloads import perturb_means
+    from workloads.configs import grad_subset
+
+    sc, disp, rig = grad_subset()
+    cams = pack_cameras(rig)
+    V = oracle.view_map(disp)
+    n = 3 * disp.width * disp.height
+    samples = np.arange(n)
+    target, _, _ = oracle.grad_subpixels(perturb_means(sc, seed=505, std=0.01), cams, disp, V, 1, samples,
+                                         mode=0, grads=False)
+
+    def loss(scene):
+        v, s, _ = oracle.grad_subpixels(scene, cams, disp, V, 1, samples, mode=0, grads=False)
+        return float(np.mean((v - target) ** 2)), s
+
+    val, sig, g = oracle.grad_subpixels(sc, cams, disp, V, 1, samples, mode=0, grads=False)
+    gout = 2.0 * (val - target) / n
+    _, sig, g = oracle.grad_subpixels(sc, cams, disp, V, 1, samples, gout, mode=0)
+    rng = np.random.Generator(np.random.PCG64(77))
+    report = {}
+    for name in oracle.GRAD_NAMES:
+        base = getattr(sc, name)
+        gflat = g[name].reshape(-1)
+        gmax = float(np.abs(gflat).max())
+        live = np.flatnonzero(np.abs(gflat) > 1e-3 * gmax)
+        picks = rng.choice(live, min(16, live.size), replace=False)
+        worst, excluded = 0.0, 0
+        for idx in picks:
+            th = float(base.reshape(-1)[idx])
+            h = 1e-6 * max(1.0, abs(th))
+            tp, tm = np.float32(th + h), np.float32(th - h)
+            Ls, same = [], True
+            for tv in (tp, tm):
+                arr = base.copy()
+                arr.reshape(-1)[idx] = tv
+                kw = {k: getattr(sc, k) for k in oracle.GRAD_NAMES}
+                kw[name] = arr
+                L, s2 = loss(Scene(**kw, sh_degree=sc.sh_degree))
+                same = same and np.array_equal(s2, sig)
+                Ls.append(L)
+            if not same:
+                excluded += 1
+                continue
+            fd = (Ls[0] - Ls[1]) / (float(tp) - float(tm))
+            worst = max(worst, abs(fd - gflat[idx]) / max(abs(gflat[idx]), 1e-3 * gmax))
+        report[name] = (len(picks), excluded, worst)
+    print("FD on the 500-Gaussian subset (checked, excluded, worst relative error):", report)
+    for name, (checked, excluded, worst) in report.items():
+        assert checked >= 8 and excluded <= 1, (name, report)
+        assert worst <= 1e-5, (name, report)
