@@ -133,9 +133,13 @@ typedef struct {
     int32_t batch_unplanned;   /* of those, rendered with host synchronization (first use of a frame slot) */
     int32_t batch_graphs;      /* of those, replayed from a captured hipGraph  */
     int32_t batch_rerendered;  /* planned frames whose pairs exceeded the plan and were rendered again */
+    int32_t batch_groups;      /* renders the batch ran (merged groups and single frames) */
     /* LFR_COUNT_WORK, remapped blend only */
     uint64_t wave_steps;       /* wavefront steps (one staged Gaussian for 64 lanes) */
     uint64_t wave_steps_live;  /* of those, steps where some lane's alpha passed the cutoff */
+    /* id of the forward the context keeps for lfr_render_backward (unique
+     * per LFR_SAVE_FOR_BACKWARD render on the context), 0 if none */
+    uint64_t saved_forward;
 } lfr_stats;
 
 /* One projected Gaussian (48 bytes), as returned by lfr_project:
@@ -235,7 +239,12 @@ typedef struct {
 /* Backward of the last lfr_render on this context, which must have been
  * called with LFR_SAVE_FOR_BACKWARD (and no other call that renders,
  * projects, sorts, tunes or trims on this context in between; otherwise
- * LFR_ERR_INVALID_ARG).  The paper defines the forward only; the backward
+ * LFR_ERR_INVALID_ARG).  saved_forward: the lfr_stats.saved_forward id read
+ * right after that render, or 0 for "whichever forward is kept"; a non-zero
+ * id that is no longer kept (another saving render came in between) is
+ * refused with LFR_ERR_INVALID_ARG, so a caller that keeps several
+ * forwards alive (e.g. two differentiable renders in one loss) cannot get
+ * the gradients of the wrong one.  The paper defines the forward only; the backward
  * is its exact derivative with the forward's discrete decisions held fixed
  * (which Gaussians pass the 1/255 cutoff, where the 1e-4 transmittance stop
  * falls, the 0.99 alpha clamp, the colour clamp at 0 and the Jacobian
@@ -244,15 +253,16 @@ typedef struct {
  * cluster).
  *
  * grad_out_device: float32 [H][W][3], dL/dI for the rendered image.
- * display and scene: the ones the forward used (same values, same M and SH
- * degree).  grads: written with dL/d(parameter); the quaternion gradient is
+ * display and scene: the ones the forward used (the same display object and
+ * the same scene arrays, unchanged since; refused otherwise).  grads: written with dL/d(parameter); the quaternion gradient is
  * with respect to the unnormalized input.  Per-(Gaussian, cluster) and
  * per-(Gaussian, view) sums use float32 atomics, so results vary in the
  * last bits between runs.  With LFR_SAVE_FOR_BACKWARD the forward bins all
  * Gaussians in one depth chunk (same image) and keeps 8 bytes per subpixel
  * (final transmittance, end of its blended list) plus its sorted lists. */
-lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
-                               const float *grad_out_device, const lfr_scene_grads *grads);
+lfr_status lfr_render_backward(lfr_context *ctx, uint64_t saved_forward, const lfr_display *display,
+                               const lfr_scene *scene, const float *grad_out_device,
+                               const lfr_scene_grads *grads);
 
 /* ---- batched frames (serving) --------------------------------------------- */
 
@@ -268,23 +278,33 @@ typedef struct {
 
 #define LFR_BATCH_GRAPH       1u  /* replay frames from captured hipGraphs      */
 #define LFR_BATCH_TIGHT_PLANS 2u  /* plan exactly the pairs seen (no headroom)  */
+#define LFR_BATCH_NO_MERGE    4u  /* render every frame on its own              */
 
-/* Render num_frames frames, in order, on the context stream, each exactly as
- * lfr_render would (same image).  Frame i uses frame slot i of the context.
- * The first time a slot sees a frame (or after its display, scene arrays,
- * options or output change) the frame is rendered with lfr_render's
- * synchronizing path and its per-depth-chunk pair counts become the slot's
- * plan (x 1.25 + 4096 capacity, exact with LFR_BATCH_TIGHT_PLANS).  Planned
- * frames run with no host synchronization and no allocation: buffers are
- * sized by the plan and every kernel reads its counts on the device.  With
- * LFR_BATCH_GRAPH each planned slot is captured once into a hipGraph and
- * replayed afterwards (cameras may change between batches; they are uploaded
- * for all frames in one copy before the frames run).  The call synchronizes
- * once at the end, checks every planned frame's pair counts against its plan,
- * and renders any frame that exceeded it again (synchronously) with a new
- * plan; lfr_stats reports how many frames took each path.  Display, scene
- * and output buffers of planned slots must stay allocated while the context
- * keeps the slots (they are rebuilt when a pointer changes). */
+/* Render num_frames frames on the context stream, each exactly as lfr_render
+ * would (same image).  Consecutive frames with the same display, scene
+ * arrays and options (the remapped blend) are merged into one render, up to
+ * 16 at a time and within a device-workspace budget (32 GB, or half the
+ * context limit when one is set): their clusters are numbered frame-major,
+ * so the frame index travels in the (tile, cluster) keys and in the blend's
+ * work items, and every stage (projection, depth sort, key generation, tile
+ * sort, ranges, blend) runs once per depth chunk for the whole group
+ * instead of once per frame (LFR_BATCH_NO_MERGE renders every frame on its
+ * own).  Group g uses batch slot g of the context.  The first time a slot
+ * sees its group (or after any of its frames' display, scene arrays,
+ * options or outputs change) the group is rendered with the synchronizing
+ * path and its per-depth-chunk pair counts become the slot's plan (x 1.25 +
+ * 4096 capacity, exact with LFR_BATCH_TIGHT_PLANS).  Planned groups run with
+ * no host synchronization and no allocation: buffers are sized by the plan
+ * and every kernel reads its counts on the device.  With LFR_BATCH_GRAPH
+ * each planned slot is captured once into a hipGraph and replayed afterwards
+ * (cameras may change between batches; they are uploaded for all frames in
+ * one copy before the groups run).  The call synchronizes once at the end,
+ * checks every planned group's pair counts against its plan, and renders
+ * any group that exceeded it again (synchronously) with a new plan;
+ * lfr_stats reports how many frames took each path and how many renders
+ * (groups) ran.  Display, scene and output buffers of planned slots must
+ * stay allocated while the context keeps the slots (they are rebuilt when
+ * a pointer changes). */
 lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames, int32_t num_frames, uint32_t flags);
 
 /* ---- autotuning ------------------------------------------------------------- */

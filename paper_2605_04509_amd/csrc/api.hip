@@ -40,7 +40,10 @@ struct Buf {
 // until the next call that uses the workspace.
 struct SavedForward {
     bool valid = false;
+    uint64_t id = 0;                  // unique per saved forward on the context
     const void *display = nullptr;
+    uint64_t display_uid = 0;
+    lfr_scene scene{};                // the scene arrays the forward read
     int64_t M = 0;
     int deg = 0;
     bool timing = false;
@@ -58,14 +61,15 @@ struct SavedForward {
     const uint32_t *save_end = nullptr;
 };
 
-// A batch frame slot: the frame it was planned for, its plan (pair capacity
-// per depth chunk) and, with LFR_BATCH_GRAPH, the captured planned frame.
+// A batch slot: the group of frames it was planned for (one frame, or frames
+// merged into one render), its plan (pair capacity per depth chunk) and, with
+// LFR_BATCH_GRAPH, the captured planned group.
 struct FrameSlot {
     const void *display = nullptr;
     uint64_t display_uid = 0;
     lfr_scene scene{};
     lfr_render_opts opts{};
-    float *out = nullptr;
+    std::vector<float *> outs;        // the group's frames' outputs
     bool tight = false;
     std::vector<uint64_t> caps;       // empty: not planned
     hipGraphExec_t graph = nullptr;
@@ -90,6 +94,7 @@ struct lfr_context {
     std::vector<FrameSlot> slots;
     Timer timer;
     SavedForward saved;
+    uint64_t next_saved_id = 1;
 };
 
 struct lfr_display {
@@ -286,27 +291,61 @@ ViewTables build_tables(const lfr_display *d, int S, bool cull)
     return vt;
 }
 
+// The tables of F frames merged into one render (a batch group): frame f's
+// view j is view f N + j, its view slot s is f N' + s and its cluster k is
+// f K' + k.  Every stage then treats the group as one render with F K'
+// clusters, and the cluster index carries the frame into the keys.
+ViewTables merge_tables(const ViewTables &vt, int F, int N)
+{
+    if (F == 1) return vt;
+    ViewTables g;
+    const int K = vt.n_clusters, NV = vt.n_views;
+    g.n_clusters = F * K;
+    g.n_views = F * NV;
+    g.cv_off.push_back(0);
+    for (int f = 0; f < F; ++f) {
+        for (int k = 0; k < K; ++k) {
+            g.cluster_rep.push_back(f * N + vt.cluster_rep[k]);
+            for (int e = vt.cv_off[k]; e < vt.cv_off[k + 1]; ++e) g.cv_list.push_back(f * NV + vt.cv_list[e]);
+            g.cv_off.push_back((int)g.cv_list.size());
+        }
+        for (int v = 0; v < NV; ++v) g.view_ids.push_back(f * N + vt.view_ids[v]);
+        for (int j = 0; j < N; ++j) {
+            g.view_slot.push_back(vt.view_slot[j] < 0 ? -1 : f * NV + vt.view_slot[j]);
+            g.view_cluster.push_back(vt.view_cluster[j] < 0 ? -1 : f * K + vt.view_cluster[j]);
+        }
+    }
+    return g;
+}
+
 // Device copy of the small per-render tables, laid out in one buffer.
 struct DevTables {
     DevCamera *cams = nullptr;
     int32_t *cluster_cam = nullptr, *view_cam = nullptr, *cv_off = nullptr, *cv_list = nullptr, *cv_cam = nullptr,
             *view_slot = nullptr, *view_cluster = nullptr;
+    float **out_frames = nullptr;     // a batch group: the frames' outputs
 };
 
-size_t tables_bytes(const lfr_display *d, const ViewTables &vt)
+// Bytes of the tables of vt (one frame or a merged group: vt.view_slot has
+// one entry per view id) with room for `n_out` output pointers.
+size_t tables_bytes(const ViewTables &vt, int n_out = 0)
 {
-    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + 2 * vt.cv_list.size() + 2 * d->N;
-    return sizeof(DevCamera) * d->N + n_int * sizeof(int32_t);
+    const size_t NT = vt.view_slot.size();
+    const size_t n_int = vt.cluster_rep.size() + vt.view_ids.size() + vt.cv_off.size() + 2 * vt.cv_list.size() + 2 * NT;
+    return sizeof(DevCamera) * NT + n_int * sizeof(int32_t) + (n_out > 0 ? 16 + sizeof(float *) * n_out : 0);
 }
 
-// Lay the tables out in host staging h for the device copy at dv.
-void write_tables(const lfr_display *d, const lfr_camera *cams, const ViewTables &vt, void *h, void *dv,
-                  DevTables *out)
+// Lay the tables out in host staging h for the device copy at dv.  cams[f]
+// holds the N cameras of frame f of the group (F = vt's view ids / N); outs
+// (n_out > 0) the frames' output pointers.
+void write_tables(const lfr_display *d, const lfr_camera *const *cams, const ViewTables &vt, void *h, void *dv,
+                  DevTables *out, float *const *outs = nullptr, int n_out = 0)
 {
     const int N = d->N;
-    const size_t cam_bytes = sizeof(DevCamera) * N;
+    const int NT = (int)vt.view_slot.size();
+    const size_t cam_bytes = sizeof(DevCamera) * NT;
     DevCamera *hc = (DevCamera *)h;
-    for (int j = 0; j < N; ++j) hc[j] = dev_camera(cams[j], d->W, d->H);
+    for (int g = 0; g < NT; ++g) hc[g] = dev_camera(cams[g / N][g % N], d->W, d->H);
     int32_t *hi = (int32_t *)((char *)h + cam_bytes);
     int32_t *di = (int32_t *)((char *)dv + cam_bytes);
     size_t o = 0;
@@ -325,16 +364,22 @@ void write_tables(const lfr_display *d, const lfr_camera *cams, const ViewTables
     put(vt.view_slot, &out->view_slot);
     put(vt.view_cluster, &out->view_cluster);
     out->cams = (DevCamera *)dv;
+    out->out_frames = nullptr;
+    if (n_out > 0) {
+        const size_t off = (cam_bytes + o * sizeof(int32_t) + 15) & ~(size_t)15;
+        memcpy((char *)h + off, outs, sizeof(float *) * n_out);
+        out->out_frames = (float **)((char *)dv + off);
+    }
 }
 
-lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camera *cams, const ViewTables &vt,
-                         DevTables *out)
+lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camera *const *cams, const ViewTables &vt,
+                         DevTables *out, float *const *outs = nullptr, int n_out = 0)
 {
-    const size_t bytes = tables_bytes(d, vt);
+    const size_t bytes = tables_bytes(vt, n_out);
     void *h = nullptr, *dv = nullptr;
     CHK(pinned_get(ctx, bytes + 64, &h));
     CHK(ws_get(ctx, kTables, bytes + 64, &dv));
-    write_tables(d, cams, vt, h, dv, out);
+    write_tables(d, cams, vt, h, dv, out, outs, n_out);
     HIPCHK(ctx, hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, ctx->stream));
     return LFR_OK;
 }
@@ -400,7 +445,9 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
     CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
     CHK(ws_get_t(ctx, kDVal1, MKp, &dval1));
-    CHK(ws_get_t(ctx, kMean2D, M * NV, &po.mean2d));
+    // (+1: the blend fetches each mean with a 16-byte load, the last one's
+    // second half past the last plane)
+    CHK(ws_get_t(ctx, kMean2D, M * NV + 1, &po.mean2d));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MKp), &sort_temp));
     const size_t e0 = tm.mark(s);
     const TileGrid tg{d->W, d->H, d->tw_shift, d->th_shift, dt.cv_off, dt.cv_list, dt.cv_cam};
@@ -423,7 +470,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
 }
 
 BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int64_t Mp, int cbits,
-                     const uint32_t *alive, const ItemRec *items, const ushort4 *ibox)
+                     const uint32_t *alive, const ItemRec *items, const ushort4 *ibox, const float2 *mean2d)
 {
     const Grid *d = &d_;
     BinParams bp;
@@ -443,6 +490,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive_words = (d->TX + 31) / 32;
     bp.items = items;
     bp.ibox = ibox;
+    bp.mean2d = mean2d;
     bp.alive_total = nullptr;
     bp.alive_sat = nullptr;
     return bp;
@@ -535,11 +583,13 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
 // Gaussians' records (one cluster, neighbouring tiles) run close together.
 constexpr int kTaskBlock = 4;
 
-lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, int n)
+lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, int n, std::vector<Task> *out)
 {
-    if (n <= 1) return LFR_OK;
-    std::vector<Task> h(n);
+    std::vector<Task> &h = *out;
+    h.resize(n);
+    if (n == 0) return LFR_OK;
     HIPCHK(ctx, hipMemcpy(h.data(), d_tasks, sizeof(Task) * n, hipMemcpyDeviceToHost));
+    if (n == 1) return LFR_OK;
     const int nbx = (d->TX + kTaskBlock - 1) / kTaskBlock;
     auto key = [&](const Task &t) {
         const int ty = (int)t.tile / d->TX, tx = (int)t.tile % d->TX;
@@ -549,6 +599,53 @@ lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, in
     };
     std::stable_sort(h.begin(), h.end(), [&](const Task &a, const Task &b) { return key(a) < key(b); });
     HIPCHK(ctx, hipMemcpy(d_tasks, h.data(), sizeof(Task) * n, hipMemcpyHostToDevice));
+    return LFR_OK;
+}
+
+// Workgroups of the blend: runs of consecutive work items of one (tile,
+// cluster) list (consecutive after ordering), at most kGroupTasks items
+// with at most kGroupViews distinct views between them.
+std::vector<TaskGroup> group_tasks(const std::vector<Task> &h)
+{
+    std::vector<TaskGroup> g;
+    for (size_t e = 0; e < h.size(); ++e) {
+        const Task &t = h[e];
+        bool join = !g.empty();
+        if (join) {
+            const TaskGroup &c = g.back();
+            const Task &f = h[c.first];
+            join = f.tile == t.tile && f.cluster == t.cluster && c.n_tasks < kGroupTasks;
+            int extra = 0;
+            for (int q = 0; q < (int)t.n_runs && join; ++q) {
+                bool seen = false;
+                for (int v = 0; v < (int)c.n_views; ++v) seen = seen || c.slot[v] == t.slot[q];
+                for (int r = 0; r < q; ++r) seen = seen || t.slot[r] == t.slot[q];
+                extra += seen ? 0 : 1;
+            }
+            join = join && (int)c.n_views + extra <= kGroupViews;
+        }
+        if (!join) {
+            TaskGroup ng{};
+            ng.first = (uint32_t)e;
+            g.push_back(ng);
+        }
+        TaskGroup &c = g.back();
+        ++c.n_tasks;
+        for (int q = 0; q < (int)t.n_runs; ++q) {
+            bool seen = false;
+            for (int v = 0; v < (int)c.n_views; ++v) seen = seen || c.slot[v] == t.slot[q];
+            if (!seen) c.slot[c.n_views++] = t.slot[q];
+        }
+    }
+    return g;
+}
+
+lfr_status upload_groups(lfr_context *ctx, const std::vector<TaskGroup> &g, TaskSet *ts)
+{
+    ts->n_groups = (int)g.size();
+    HIPCHK(ctx, hipMalloc((void **)&ts->d_groups, sizeof(TaskGroup) * std::max<size_t>(g.size(), 1)));
+    if (!g.empty())
+        HIPCHK(ctx, hipMemcpy(ts->d_groups, g.data(), sizeof(TaskGroup) * g.size(), hipMemcpyHostToDevice));
     return LFR_OK;
 }
 
@@ -609,7 +706,92 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
                                  ts.d_tasks, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ts.n = (int)n;
-    CHK(order_tasks(ctx, d, ts.d_tasks, ts.n));
+    std::vector<Task> h;
+    CHK(order_tasks(ctx, d, ts.d_tasks, ts.n, &h));
+    {
+        const lfr_status gs = upload_groups(ctx, group_tasks(h), &ts);
+        if (ts.d_groups) guard.owned.push_back(ts.d_groups);
+        CHK(gs);
+    }
+    guard.keep = true;
+    auto ins = d->tasks.emplace(key, ts);
+    *out = &ins.first->second;
+    return LFR_OK;
+}
+
+// The work items and per-(tile, cluster) subpixel counts of F frames merged
+// into one render (a batch group): F copies of the display's items with
+// cluster f K' + k, mean slots f N' + s and the frame index, laid out frame
+// after frame; counts under the group's cluster bits.  Built once per
+// display, cluster size, culling and F.
+lfr_status get_group_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, int F,
+                            TaskSet **out)
+{
+    TaskSet *base = nullptr;
+    CHK(get_layout(ctx, d, S, cull, vt, &base));
+    if (F == 1) {
+        *out = base;
+        return LFR_OK;
+    }
+    const int64_t key = ((int64_t)F << 32) | ((int64_t)S * 2 + (cull ? 1 : 0));
+    auto it = d->tasks.find(key);
+    if (it != d->tasks.end()) {
+        *out = &it->second;
+        return LFR_OK;
+    }
+    const int K = vt.n_clusters, NV = vt.n_views;
+    const int cb1 = base->cluster_bits, cbg = bits_for((int64_t)F * K);
+    std::vector<Task> h1(std::max(base->n, 1));
+    std::vector<uint32_t> c1((size_t)d->T << cb1);
+    if (base->n) HIPCHK(ctx, hipMemcpy(h1.data(), base->d_tasks, sizeof(Task) * base->n, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(c1.data(), base->d_tc_count, sizeof(uint32_t) * c1.size(), hipMemcpyDeviceToHost));
+    std::vector<Task> hg((size_t)F * base->n);
+    std::vector<uint32_t> cg((size_t)d->T << cbg, 0u);
+    for (int f = 0; f < F; ++f) {
+        for (int e = 0; e < base->n; ++e) {
+            Task t = h1[e];
+            t.cluster += (uint32_t)(f * K);
+            for (int q = 0; q < (int)t.n_runs; ++q) t.slot[q] = (uint16_t)(t.slot[q] + f * NV);
+            t.frame = (uint32_t)f;
+            hg[(size_t)f * base->n + e] = t;
+        }
+        for (int64_t t = 0; t < d->T; ++t)
+            for (int k = 0; k < K; ++k) cg[(size_t)(t << cbg) | (size_t)(f * K + k)] = c1[(size_t)(t << cb1) | k];
+    }
+    std::vector<TaskGroup> g1(std::max(base->n_groups, 1));
+    if (base->n_groups)
+        HIPCHK(ctx, hipMemcpy(g1.data(), base->d_groups, sizeof(TaskGroup) * base->n_groups, hipMemcpyDeviceToHost));
+    std::vector<TaskGroup> gg;
+    for (int f = 0; f < F; ++f)
+        for (int e = 0; e < base->n_groups; ++e) {
+            TaskGroup t = g1[e];
+            t.first += (uint32_t)(f * base->n);
+            for (int v = 0; v < (int)t.n_views; ++v) t.slot[v] = (uint16_t)(t.slot[v] + f * NV);
+            gg.push_back(t);
+        }
+    TaskSet ts;
+    ts.cluster_bits = cbg;
+    ts.n = F * base->n;
+    struct Guard {
+        std::vector<void *> p;
+        bool keep = false;
+        ~Guard()
+        {
+            if (!keep)
+                for (void *q : p) (void)hipFree(q);
+        }
+    } guard;
+    HIPCHK(ctx, hipMalloc((void **)&ts.d_tasks, sizeof(Task) * std::max<size_t>(hg.size(), 1)));
+    guard.p.push_back(ts.d_tasks);
+    HIPCHK(ctx, hipMalloc((void **)&ts.d_tc_count, sizeof(uint32_t) * cg.size()));
+    guard.p.push_back(ts.d_tc_count);
+    if (!hg.empty()) HIPCHK(ctx, hipMemcpy(ts.d_tasks, hg.data(), sizeof(Task) * hg.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(ts.d_tc_count, cg.data(), sizeof(uint32_t) * cg.size(), hipMemcpyHostToDevice));
+    {
+        const lfr_status gs = upload_groups(ctx, gg, &ts);
+        if (ts.d_groups) guard.p.push_back(ts.d_groups);
+        CHK(gs);
+    }
     guard.keep = true;
     auto ins = d->tasks.emplace(key, ts);
     *out = &ins.first->second;
@@ -701,10 +883,15 @@ struct FrameRun {
     std::vector<uint64_t> *chunk_pairs = nullptr;
 };
 
-// One frame of the subpixel renderer (appendix B.2 algorithm).  Arguments are
-// already validated.  `run` (may be null) selects how it runs: see FrameRun.
-lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
-                        const lfr_camera *host_cams, const lfr_render_opts *opts, float *out_device,
+// F frames of the subpixel renderer (appendix B.2 algorithm) as one render:
+// frames that share the display, the scene and the options and differ only
+// in their cameras (cams[f], outs[f]).  With F > 1 the frames are merged:
+// their clusters are numbered f K' + k (merge_tables), so one launch of each
+// stage serves every frame.  F > 1 needs the remapped blend and neither
+// saving nor counting.  Arguments are already validated.  `run` (may be
+// null) selects how it runs: see FrameRun.
+lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene, int F,
+                        const lfr_camera *const *cams, const lfr_render_opts *opts, float *const *outs,
                         const FrameRun *run)
 {
     lfr_display *d = const_cast<lfr_display *>(display);
@@ -714,21 +901,24 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     const bool remap = (opts->flags & LFR_REMAP) != 0;
     const bool count = (opts->flags & LFR_COUNT_WORK) != 0;
     const bool save = (opts->flags & LFR_SAVE_FOR_BACKWARD) != 0;
+    if (F < 1 || (F > 1 && (!remap || count || save)))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "merged frames need the remapped blend, without saving or counting");
     const int S = opts->cluster_size;
     const int64_t M = scene->num_gaussians;
-    const int64_t nsub = 3ll * d->W * d->H;
+    const int64_t nsub = 3ll * d->W * d->H, nsub_all = nsub * F;
     ctx->stats = lfr_stats{};
     Timer &tm = ctx->timer;
-    const ViewTables vt = build_tables(d, S, cull);
+    const ViewTables vt1 = build_tables(d, S, cull);
+    const ViewTables vt = merge_tables(vt1, F, d->N);
     TaskSet *ts = nullptr;
-    CHK(get_layout(ctx, d, S, cull, vt, &ts));
+    CHK(get_group_layout(ctx, d, S, cull, vt1, F, &ts));
     tm.reset(!planned && (opts->flags & LFR_TIMING) != 0);
     const size_t t0 = tm.mark(s);
     DevTables dt;
     if (run && run->tables)
         dt = *run->tables;
     else
-        CHK(upload_tables(ctx, d, host_cams, vt, &dt));
+        CHK(upload_tables(ctx, d, cams, vt, &dt, outs, F > 1 ? F : 0));
     Projected pr;
     CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, &pr));
 
@@ -742,13 +932,13 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     Totals *d_tot;
     CHK(ws_get_t(ctx, kAlive, n_tc, &tc_alive));
     CHK(ws_get_t(ctx, kAliveBits, (int64_t)vt.n_clusters * d->TY * words, &alive_bits));
-    CHK(ws_get_t(ctx, kState, nsub, &state));
+    CHK(ws_get_t(ctx, kState, nsub_all, &state));
     CHK(ws_get_t(ctx, kTaskAlive, (size_t)std::max(ts->n, 1) + 4, &task_alive));
     CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
     // per-frame traversal state: every list and subpixel unsaturated
     auto reset_state = [&]() -> lfr_status {
         HIPCHK(ctx, launch_copy_u32(tc_alive, ts->d_tc_count, n_tc, s));
-        HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub, 1, s));
+        HIPCHK(ctx, launch_fill_u32(&d_tot->alive, (uint32_t)nsub_all, 1, s));
         HIPCHK(ctx, launch_fill_u32((uint32_t *)task_alive, 0x01010101u, (std::max(ts->n, 1) + 3) / 4, s));
         HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
         return LFR_OK;
@@ -772,7 +962,9 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     bp.rec = pr.rec;
     bp.mean2d = pr.mean2d;
     for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
-    bp.out = out_device;
+    bp.out = outs[0];
+    bp.out_frames = F > 1 ? dt.out_frames : nullptr;
+    bp.n_sub = nsub;
     bp.work = nullptr;
     bp.state = state;
     bp.task_alive = task_alive;
@@ -788,7 +980,7 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
         CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
         CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
     }
-    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox);
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox, pr.mean2d);
     if (planned) bin.alive_total = &d_tot->alive;
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x.
@@ -832,7 +1024,7 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
             bp.last = last ? 1 : 0;
             const size_t e0 = tm.mark(s);
             if (remap)
-                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
+                HIPCHK(ctx, launch_blend_group(bp, ts->d_tasks, ts->d_groups, ts->n_groups, s));
             else
                 HIPCHK(ctx, launch_blend_rowmajor(bp, s));
             const size_t e1 = tm.mark(s);
@@ -873,7 +1065,10 @@ lfr_status render_frame(lfr_context *ctx, const lfr_display *display, const lfr_
     tm.span(kStTotal, t0, tm.mark(s));
     if (save) {
         SavedForward &sv = ctx->saved;
+        sv.id = ctx->next_saved_id++;
         sv.display = d;
+        sv.display_uid = d->uid;
+        sv.scene = *scene;
         sv.M = M;
         sv.deg = scene->sh_degree;
         sv.timing = (opts->flags & LFR_TIMING) != 0;
@@ -985,6 +1180,7 @@ lfr_status lfr_get_stats(const lfr_context *ctx, lfr_stats *out)
     if (!ctx || !out) return LFR_ERR_INVALID_ARG;
     *out = ctx->stats;
     out->workspace_bytes = ws_total(ctx);
+    out->saved_forward = ctx->saved.valid ? ctx->saved.id : 0;
     return LFR_OK;
 }
 
@@ -1135,6 +1331,7 @@ void lfr_display_destroy(lfr_display *d)
         if (kv.second.d_tasks) (void)hipFree(kv.second.d_tasks);
         if (kv.second.d_view_cluster) (void)hipFree(kv.second.d_view_cluster);
         if (kv.second.d_tc_count) (void)hipFree(kv.second.d_tc_count);
+        if (kv.second.d_groups) (void)hipFree(kv.second.d_groups);
     }
     delete d;
 }
@@ -1200,11 +1397,11 @@ lfr_status lfr_render(lfr_context *ctx, const lfr_display *display, const lfr_sc
 {
     CHK(begin(ctx));
     CHK(check_render_args(ctx, display, scene, host_cams, num_cams, opts, out_device));
-    return render_frame(ctx, display, scene, host_cams, opts, out_device, nullptr);
+    return render_group(ctx, display, scene, 1, &host_cams, opts, &out_device, nullptr);
 }
 
-lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, const lfr_scene *scene,
-                               const float *grad_out_device, const lfr_scene_grads *grads)
+lfr_status lfr_render_backward(lfr_context *ctx, uint64_t saved_forward, const lfr_display *display,
+                               const lfr_scene *scene, const float *grad_out_device, const lfr_scene_grads *grads)
 {
     CHK(begin(ctx, true));
     const SavedForward &sv = ctx->saved;
@@ -1212,12 +1409,19 @@ lfr_status lfr_render_backward(lfr_context *ctx, const lfr_display *display, con
         return fail(ctx, LFR_ERR_INVALID_ARG,
                     "no saved forward: call lfr_render with LFR_SAVE_FOR_BACKWARD first (and nothing that uses "
                     "this context's workspace in between)");
-    if (!display || (const void *)display != sv.display)
+    if (saved_forward != 0 && saved_forward != sv.id)
+        return fail(ctx, LFR_ERR_INVALID_ARG,
+                    "saved forward %llu is no longer kept (the context now keeps forward %llu): a later render "
+                    "replaced it", (unsigned long long)saved_forward, (unsigned long long)sv.id);
+    if (!display || (const void *)display != sv.display || display->uid != sv.display_uid)
         return fail(ctx, LFR_ERR_INVALID_ARG, "display differs from the saved forward's");
     CHK(check_scene(ctx, scene));
     if (scene->num_gaussians != sv.M || scene->sh_degree != sv.deg)
         return fail(ctx, LFR_ERR_INVALID_ARG, "scene (M %lld, degree %d) differs from the saved forward's (M %lld, "
                     "degree %d)", (long long)scene->num_gaussians, scene->sh_degree, (long long)sv.M, sv.deg);
+    if (scene->means != sv.scene.means || scene->log_scales != sv.scene.log_scales ||
+        scene->quats != sv.scene.quats || scene->opacities != sv.scene.opacities || scene->sh != sv.scene.sh)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "scene arrays differ from the ones the saved forward read");
     if (!grad_out_device) return fail(ctx, LFR_ERR_INVALID_ARG, "grad_out is NULL");
     if (!grads) return fail(ctx, LFR_ERR_INVALID_ARG, "grads is NULL");
     const int64_t M = sv.M;
@@ -1309,7 +1513,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
             vt.view_cluster[j] = b;
         }
         DevTables dt;
-        CHK(upload_tables(ctx, d, host_cams, vt, &dt));
+        CHK(upload_tables(ctx, d, &host_cams, vt, &dt));
         Projected pr;
         CHK(project_and_sort(ctx, fg, scene, dt, vt, &pr));
         // one chunk with every tile of every view alive
@@ -1318,7 +1522,7 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
-        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox);
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox, pr.mean2d);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;
@@ -1477,7 +1681,13 @@ lfr_status lfr_sort_pairs_u64(lfr_context *ctx, uint64_t *keys, uint32_t *vals, 
 // ---------------------------------------------------------------------------
 namespace {
 
-// Number of depth chunks render_frame runs for M Gaussians.
+// Frames merged into one render at most, and the device workspace a merged
+// group may plan for (its per-(Gaussian, cluster) and per-(Gaussian, view)
+// planes; half the context limit when one is set).
+constexpr int kMaxGroupFrames = 16;
+constexpr uint64_t kGroupBudget = 32ull << 30;
+
+// Number of depth chunks render_group runs for M Gaussians.
 int chunk_count(int64_t M, int32_t first_chunk)
 {
     int64_t r0 = 0, len = first_chunk > 0 ? (int64_t)first_chunk
@@ -1515,11 +1725,28 @@ void drop_graph(FrameSlot &sl)
     sl.graph = nullptr;
 }
 
-bool same_frame(const FrameSlot &sl, const lfr_frame &f, bool tight)
+// Frames a and b render with the same display, scene arrays and options.
+bool mergeable(const lfr_frame &a, const lfr_frame &b)
 {
-    return sl.display == (const void *)f.display && sl.display_uid == f.display->uid &&
-           memcmp(&sl.scene, f.scene, sizeof(lfr_scene)) == 0 && memcmp(&sl.opts, &f.opts, sizeof(lfr_render_opts)) == 0 &&
-           sl.out == f.out_device && sl.tight == tight;
+    return a.display == b.display && a.display->uid == b.display->uid &&
+           memcmp(a.scene, b.scene, sizeof(lfr_scene)) == 0 && memcmp(&a.opts, &b.opts, sizeof(lfr_render_opts)) == 0;
+}
+
+// A batch group: frames [first, first + count) rendered as one render.
+struct Group {
+    int first = 0, count = 0;
+};
+
+bool same_group(const FrameSlot &sl, const lfr_frame *f, const Group &g, bool tight)
+{
+    if ((int)sl.outs.size() != g.count || sl.tight != tight) return false;
+    const lfr_frame &a = f[g.first];
+    if (sl.display != (const void *)a.display || sl.display_uid != a.display->uid ||
+        memcmp(&sl.scene, a.scene, sizeof(lfr_scene)) != 0 || memcmp(&sl.opts, &a.opts, sizeof(lfr_render_opts)) != 0)
+        return false;
+    for (int e = 0; e < g.count; ++e)
+        if (sl.outs[e] != f[g.first + e].out_device) return false;
+    return true;
 }
 
 // Plan from an unplanned render's per-chunk pair counts.
@@ -1530,9 +1757,32 @@ void set_plan(FrameSlot &sl, const std::vector<uint64_t> &pairs, bool tight)
         sl.caps[c] = tight ? pairs[c] : pairs[c] + pairs[c] / 4 + 4096;
 }
 
-// Capture one planned frame into a graph.  On failure (e.g. the workspace
+// The cameras and outputs of a group, as render_group takes them.
+struct GroupArgs {
+    std::vector<const lfr_camera *> cams;
+    std::vector<float *> outs;
+};
+GroupArgs group_args(const lfr_frame *f, const Group &g)
+{
+    GroupArgs a;
+    for (int e = 0; e < g.count; ++e) {
+        a.cams.push_back(f[g.first + e].host_cams);
+        a.outs.push_back(f[g.first + e].out_device);
+    }
+    return a;
+}
+
+lfr_status run_group(lfr_context *ctx, const lfr_frame *f, const Group &g, const FrameRun &run)
+{
+    const GroupArgs a = group_args(f, g);
+    const lfr_frame &h = f[g.first];
+    return render_group(ctx, h.display, h.scene, g.count, a.cams.data(), &h.opts, a.outs.data(), &run);
+}
+
+// Capture one planned group into a graph.  On failure (e.g. the workspace
 // would have to grow) the capture is discarded and *exec stays null.
-lfr_status capture_frame(lfr_context *ctx, const lfr_frame &f, const FrameRun &run, hipGraphExec_t *exec)
+lfr_status capture_group(lfr_context *ctx, const lfr_frame *f, const Group &g, const FrameRun &run,
+                         hipGraphExec_t *exec)
 {
     *exec = nullptr;
     if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -1540,19 +1790,19 @@ lfr_status capture_frame(lfr_context *ctx, const lfr_frame &f, const FrameRun &r
     const hipStream_t user = ctx->stream;
     ctx->stream = ctx->cap_stream;
     ctx->capturing = true;
-    const lfr_status st = render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run);
+    const lfr_status st = run_group(ctx, f, g, run);
     ctx->capturing = false;
     ctx->stream = user;
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
-    if (st != LFR_OK || ec != hipSuccess || !g) {
-        if (g) (void)hipGraphDestroy(g);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &gr);
+    if (st != LFR_OK || ec != hipSuccess || !gr) {
+        if (gr) (void)hipGraphDestroy(gr);
         (void)hipGetLastError();
         ctx->err.clear();
         return LFR_OK;
     }
-    const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
+    const hipError_t ei = hipGraphInstantiate(exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
     if (ei != hipSuccess) {
         *exec = nullptr;
         (void)hipGetLastError();
@@ -1567,7 +1817,8 @@ extern "C" lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames
     CHK(begin(ctx));
     if (num_frames < 0 || (num_frames > 0 && !frames))
         return fail(ctx, LFR_ERR_INVALID_ARG, "bad frame list");
-    if (flags & ~(LFR_BATCH_GRAPH | LFR_BATCH_TIGHT_PLANS)) return fail(ctx, LFR_ERR_INVALID_ARG, "unknown batch flags");
+    if (flags & ~(LFR_BATCH_GRAPH | LFR_BATCH_TIGHT_PLANS | LFR_BATCH_NO_MERGE))
+        return fail(ctx, LFR_ERR_INVALID_ARG, "unknown batch flags");
     for (int i = 0; i < num_frames; ++i) {
         const lfr_frame &f = frames[i];
         CHK(check_render_args(ctx, f.display, f.scene, f.host_cams, f.num_cams, &f.opts, f.out_device));
@@ -1576,102 +1827,136 @@ extern "C" lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames
                         "available in a batch", i);
     }
     const bool use_graph = (flags & LFR_BATCH_GRAPH) != 0, tight = (flags & LFR_BATCH_TIGHT_PLANS) != 0;
+    const bool merge = (flags & LFR_BATCH_NO_MERGE) == 0;
     hipStream_t s = ctx->stream;
-    if ((int)ctx->slots.size() < num_frames) ctx->slots.resize(num_frames);
-    int n_unplanned = 0, n_graphs = 0, n_rerendered = 0;
 
-    // every frame's camera tables, uploaded in one copy
-    std::vector<ViewTables> vts(num_frames);
-    std::vector<size_t> offs(num_frames);
-    size_t total = 0;
-    for (int i = 0; i < num_frames; ++i) {
+    // groups: runs of consecutive frames with the same display, scene and
+    // options (remapped blend), as many as the key bits and the workspace
+    // budget allow; every other frame is a group of one
+    const uint64_t budget = ctx->limit ? ctx->limit / 2 : kGroupBudget;
+    std::vector<Group> groups;
+    std::vector<ViewTables> vt1s;
+    for (int i = 0; i < num_frames;) {
         const lfr_frame &f = frames[i];
         lfr_display *d = const_cast<lfr_display *>(f.display);
         const bool cull = (f.opts.flags & LFR_CULL_UNREFERENCED) != 0;
-        vts[i] = build_tables(d, f.opts.cluster_size, cull);
+        ViewTables vt1 = build_tables(d, f.opts.cluster_size, cull);
+        const uint64_t M = (uint64_t)f.scene->num_gaussians;
+        const uint64_t per_frame = M * (120ull * vt1.n_clusters + 8ull * vt1.n_views) + 16ull * d->W * d->H * 3;
+        const int tbits = bits_for(d->T);
+        Group g{i, 1};
+        if (merge && (f.opts.flags & LFR_REMAP))
+            while (g.count < kMaxGroupFrames && i + g.count < num_frames && mergeable(f, frames[i + g.count]) &&
+                   per_frame * (uint64_t)(g.count + 1) <= budget &&
+                   bits_for((int64_t)(g.count + 1) * vt1.n_clusters) + tbits <= 32)
+                ++g.count;
+        groups.push_back(g);
+        vt1s.push_back(std::move(vt1));
+        i += g.count;
+    }
+    const int n_groups = (int)groups.size();
+    if ((int)ctx->slots.size() < n_groups) ctx->slots.resize(n_groups);
+    int n_unplanned = 0, n_graphs = 0, n_rerendered = 0;
+
+    // every group's tables (cameras, cluster/view tables, output pointers),
+    // uploaded in one copy
+    std::vector<ViewTables> vts(n_groups);
+    std::vector<size_t> offs(n_groups);
+    size_t total = 0;
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const Group &g = groups[gi];
+        const lfr_frame &f = frames[g.first];
+        lfr_display *d = const_cast<lfr_display *>(f.display);
+        const bool cull = (f.opts.flags & LFR_CULL_UNREFERENCED) != 0;
         TaskSet *ts = nullptr;
-        CHK(get_layout(ctx, d, f.opts.cluster_size, cull, vts[i], &ts));
-        offs[i] = total;
-        total += (tables_bytes(d, vts[i]) + 255) & ~(size_t)255;
+        CHK(get_group_layout(ctx, d, f.opts.cluster_size, cull, vt1s[gi], g.count, &ts));
+        vts[gi] = merge_tables(vt1s[gi], g.count, d->N);
+        offs[gi] = total;
+        total += (tables_bytes(vts[gi], g.count > 1 ? g.count : 0) + 255) & ~(size_t)255;
     }
     void *dtab = nullptr, *htab = nullptr;
     uint64_t *need = nullptr;
     CHK(ws_get(ctx, kBatchTables, std::max<size_t>(total, 256), &dtab));
-    CHK(ws_get_t(ctx, kBatchNeed, (size_t)std::max(num_frames, 1) * kMaxPlannedChunks, &need));
+    CHK(ws_get_t(ctx, kBatchNeed, (size_t)std::max(n_groups, 1) * kMaxPlannedChunks, &need));
     CHK(batch_pinned_get(ctx, std::max<size_t>(total, 256), &htab));
-    std::vector<DevTables> dts(num_frames);
-    for (int i = 0; i < num_frames; ++i)
-        write_tables(frames[i].display, frames[i].host_cams, vts[i], (char *)htab + offs[i], (char *)dtab + offs[i],
-                     &dts[i]);
+    std::vector<DevTables> dts(n_groups);
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const GroupArgs a = group_args(frames, groups[gi]);
+        const int n_out = groups[gi].count > 1 ? groups[gi].count : 0;
+        write_tables(frames[groups[gi].first].display, a.cams.data(), vts[gi], (char *)htab + offs[gi],
+                     (char *)dtab + offs[gi], &dts[gi], a.outs.data(), n_out);
+    }
     if (total) HIPCHK(ctx, hipMemcpyAsync(dtab, htab, total, hipMemcpyHostToDevice, s));
 
     std::vector<int> planned;
-    for (int i = 0; i < num_frames; ++i) {
-        const lfr_frame &f = frames[i];
-        FrameSlot &sl = ctx->slots[i];
-        if (!same_frame(sl, f, tight)) {
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const Group &g = groups[gi];
+        const lfr_frame &f = frames[g.first];
+        FrameSlot &sl = ctx->slots[gi];
+        if (!same_group(sl, frames, g, tight)) {
             drop_graph(sl);
             sl.caps.clear();
             sl.display = f.display;
             sl.display_uid = f.display->uid;
             sl.scene = *f.scene;
             sl.opts = f.opts;
-            sl.out = f.out_device;
+            sl.outs = group_args(frames, g).outs;
             sl.tight = tight;
         }
         FrameRun run;
-        run.tables = &dts[i];
+        run.tables = &dts[gi];
         if (sl.caps.empty() || chunk_count(f.scene->num_gaussians, f.opts.first_chunk) > kMaxPlannedChunks) {
             std::vector<uint64_t> pairs;
             run.chunk_pairs = &pairs;
-            CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
+            CHK(run_group(ctx, frames, g, run));
             set_plan(sl, pairs, tight);
-            ++n_unplanned;
+            n_unplanned += g.count;
             continue;
         }
         run.caps = &sl.caps;
-        run.d_need = need + (size_t)i * kMaxPlannedChunks;
+        run.d_need = need + (size_t)gi * kMaxPlannedChunks;
         if (use_graph) {
-            if (sl.graph && (sl.graph_gen != ctx->ws_gen || sl.graph_table_off != offs[i])) drop_graph(sl);
+            if (sl.graph && (sl.graph_gen != ctx->ws_gen || sl.graph_table_off != offs[gi])) drop_graph(sl);
             if (!sl.graph) {
-                CHK(capture_frame(ctx, f, run, &sl.graph));
+                CHK(capture_group(ctx, frames, g, run, &sl.graph));
                 sl.graph_gen = ctx->ws_gen;
-                sl.graph_table_off = offs[i];
+                sl.graph_table_off = offs[gi];
             }
             if (sl.graph) {
                 HIPCHK(ctx, hipGraphLaunch(sl.graph, s));
-                ++n_graphs;
-                planned.push_back(i);
+                n_graphs += g.count;
+                planned.push_back(gi);
                 continue;
             }
         }
-        CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
-        planned.push_back(i);
+        CHK(run_group(ctx, frames, g, run));
+        planned.push_back(gi);
     }
 
-    // one synchronization: check the planned frames' pair counts
-    std::vector<uint64_t> hneed((size_t)std::max(num_frames, 1) * kMaxPlannedChunks);
+    // one synchronization: check the planned groups' pair counts
+    std::vector<uint64_t> hneed((size_t)std::max(n_groups, 1) * kMaxPlannedChunks);
     if (!planned.empty())
         HIPCHK(ctx, hipMemcpyAsync(hneed.data(), need, hneed.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    for (int i : planned) {
-        const lfr_frame &f = frames[i];
-        FrameSlot &sl = ctx->slots[i];
+    for (int gi : planned) {
+        const Group &g = groups[gi];
+        const lfr_frame &f = frames[g.first];
+        FrameSlot &sl = ctx->slots[gi];
         const int nc = chunk_count(f.scene->num_gaussians, f.opts.first_chunk);
         bool over = false;
         for (int c = 0; c < nc; ++c) {
             const uint64_t cap = c < (int)sl.caps.size() ? sl.caps[c] : kUnplannedChunkCap;
-            over = over || hneed[(size_t)i * kMaxPlannedChunks + c] > std::max<uint64_t>(cap, 1);
+            over = over || hneed[(size_t)gi * kMaxPlannedChunks + c] > std::max<uint64_t>(cap, 1);
         }
         if (!over) continue;
         drop_graph(sl);
         FrameRun run;
-        run.tables = &dts[i];
+        run.tables = &dts[gi];
         std::vector<uint64_t> pairs;
         run.chunk_pairs = &pairs;
-        CHK(render_frame(ctx, f.display, f.scene, f.host_cams, &f.opts, f.out_device, &run));
+        CHK(run_group(ctx, frames, g, run));
         set_plan(sl, pairs, tight);
-        ++n_rerendered;
+        n_rerendered += g.count;
     }
     if (n_rerendered) HIPCHK(ctx, hipStreamSynchronize(s));
     ctx->stats = lfr_stats{};
@@ -1679,6 +1964,7 @@ extern "C" lfr_status lfr_render_batch(lfr_context *ctx, const lfr_frame *frames
     ctx->stats.batch_unplanned = n_unplanned;
     ctx->stats.batch_graphs = n_graphs;
     ctx->stats.batch_rerendered = n_rerendered;
+    ctx->stats.batch_groups = n_groups;
     ctx->stats.workspace_bytes = ws_total(ctx);
     return LFR_OK;
 }

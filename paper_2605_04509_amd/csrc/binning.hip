@@ -67,11 +67,14 @@ __device__ inline bool row_span(const ItemRec &r, float2 m, int y0, int y1, int 
     return true;
 }
 
-// Tiles of the item in unit u: the OR over its views of the tiles in the
-// unit's row and word that the view's ellipse span covers (or the bounding
-// box when the record holds too few views), restricted to alive lists.
-// Also returns the unit's row and word.
-__device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &r, int u, int &ty, int &w)
+// Tiles of the item (Gaussian i, cluster k) in unit u: the OR over the
+// cluster's views of the tiles in the unit's row and word that the view's
+// ellipse span covers, restricted to alive lists.  The record holds the
+// means of up to kItemViews views whose boxes meet the panel; when the
+// cluster has more such views (flags bit 0), every view's mean is read from
+// the mean planes instead (an invalid view's far stand-in mean covers
+// nothing).  Also returns the unit's row and word.
+__device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, const ItemRec &r, int u, int &ty, int &w)
 {
     const int w0 = (int)r.bbox.x >> 5;
     const int nw = ((int)r.bbox.y >> 5) - w0 + 1;
@@ -88,18 +91,25 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, const ItemRec &
         const uint32_t ml = lo <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << lo);
         return mh & ml;
     };
+    // the unit's word clipped to the item's box
+    const uint32_t box = bits((int)r.bbox.x, (int)r.bbox.y);
     uint32_t m = 0;
+    const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
     if (r.flags) {
-        m = bits((int)r.bbox.x, (int)r.bbox.y);
+        for (int v = bp.cv_off[k]; v < bp.cv_off[k + 1]; ++v) {
+            const float2 mv = bp.mean2d[(int64_t)bp.cv_list[v] * bp.M + i];
+            int c0, c1;
+            if (row_span(r, mv, y0, y1, bp.W, c0, c1))
+                m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
+        }
     } else {
-        const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
         for (int v = 0; v < (int)r.nv; ++v) {
             int c0, c1;
             if (row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
         }
     }
     const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;
-    return m & alive_k[(int64_t)ty * bp.alive_words + w];
+    return m & box & alive_k[(int64_t)ty * bp.alive_words + w];
 }
 
 // The record of lane `owner`, handed over through lane exchanges (the lanes
@@ -220,7 +230,7 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         int ty = 0, w = 0;
         uint32_t m = 0;
         const ItemRec rown = shfl_item(own, owner);
-        if (has) m = unit_mask(bp, k, rown, (int)uloc, ty, w);
+        if (has) m = unit_mask(bp, k, iown, rown, (int)uloc, ty, w);
         const uint32_t c = (uint32_t)__popc(m);
         if (!kEmit) {
             if (c) atomicAdd(&s_cnt[wave][owner], c);

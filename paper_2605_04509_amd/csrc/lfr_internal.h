@@ -26,6 +26,10 @@ constexpr double kHalfLog2e = 0.5 * 1.44269504088896340736;
 constexpr int kMaxClusterViews = 32;        // views unioned per cluster
 constexpr int kMaxWaveViews = 4;            // distinct views in one blend wavefront
 constexpr int kWave = 64;
+// Stand-in for a 2D mean that is invalid in a view: far outside any panel,
+// so E = +inf and alpha = 0 wherever it is evaluated, and no tile or row span
+// contains it.
+constexpr float kFarMean = 1e30f;
 
 // Camera in double precision, with the derived clamp limits and centre.
 struct DevCamera {
@@ -64,9 +68,23 @@ struct alignas(16) Task {
     uint16_t n_runs;       // distinct views, 1..kMaxWaveViews
     uint8_t run_start[4];  // first lane of run q; 64 for q >= n_runs
     uint16_t slot[4];      // compact mean slot of run q's view (0 for q >= n_runs)
-    uint32_t pad;
+    uint32_t frame;        // frame of a merged batch group (0 otherwise)
 };
 static_assert(sizeof(Task) == 32, "Task must be 32 bytes");
+
+// The blend work items of one (tile, cluster) list that run as one
+// workgroup sharing each fetched batch: up to kGroupTasks consecutive items
+// with up to kGroupViews distinct views between them.
+constexpr int kGroupTasks = 8;
+constexpr int kGroupViews = 8;
+struct alignas(16) TaskGroup {
+    uint32_t first;                // first item
+    uint16_t n_tasks;              // 1..kGroupTasks
+    uint16_t n_views;              // 1..kGroupViews
+    uint16_t slot[kGroupViews];    // compact mean slots of the views (0 beyond n_views)
+    uint32_t pad[2];
+};
+static_assert(sizeof(TaskGroup) == 32, "TaskGroup must be 32 bytes");
 
 // Per-render cluster/view tables (device copies live in the context).
 struct ViewTables {
@@ -85,6 +103,8 @@ struct ViewTables {
 struct TaskSet {
     Task *d_tasks = nullptr;
     int n = 0;
+    TaskGroup *d_groups = nullptr;        // the items grouped by (tile, cluster) list
+    int n_groups = 0;
     int32_t *d_view_cluster = nullptr;    // [N]
     uint32_t *d_tc_count = nullptr;       // [T << cluster_bits]
     int cluster_bits = 0;
@@ -171,7 +191,7 @@ hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_
 // the 2D mean in each view whose box is non-empty (up to kItemViews).  Binning
 // covers, per tile row and view, the x-range of the cutoff ellipse over that
 // row; with more non-empty views than fit, `flags` bit 0 is set and binning
-// covers the bounding box (still conservative).  64 B aligned.
+// reads every view's mean from the mean planes.  64 B aligned.
 constexpr int kItemViews = 4;
 struct alignas(64) ItemRec {
     uint16_t nv;
@@ -195,7 +215,7 @@ struct ProjectOut {
     ushort4 *ibox;      // [K'][M]  the records' union tile boxes (read alone to skip saturated items)
     uint32_t *dkey;     // [K'][Mp] float32 depth bits, 0xFFFFFFFF if invalid or padding
     uint32_t *dval;     // [K'][Mp] Gaussian index
-    float2 *mean2d;     // [N'][M]  NaN if the mean is invalid
+    float2 *mean2d;     // [N'][M]  (kFarMean, kFarMean) if the mean is invalid
     int64_t Mp;         // M rounded up to the sort's segment granule
 };
 struct TileGrid {
@@ -245,6 +265,7 @@ struct BinParams {
     int alive_words;          // 32-bit words per tile row
     const ItemRec *items;     // [K'][M]
     const ushort4 *ibox;      // [K'][M] union tile box of each record
+    const float2 *mean2d;     // [N'][M] per-view means (records with more views than they hold)
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
 };
@@ -281,6 +302,8 @@ struct BlendParams {
     const float2 *mean2d;         // [N'][M]
     float bg[3];
     float *out;                   // [H][W][3]
+    float *const *out_frames;     // merged batch group: output of each frame (null: out)
+    int64_t n_sub;                // 3 W H: per-frame stride of the traversal state
     unsigned long long *work;     // [2] evals, blended (counting variant only)
     // resumable traversal over depth chunks
     float2 *state;                // per subpixel (T, C); T < 0 once saturated
@@ -293,6 +316,8 @@ struct BlendParams {
     uint32_t *save_end;           // per subpixel: 1 + position of its last blended pair (0: none)
 };
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
+                              hipStream_t s);
+hipError_t launch_blend_group(const BlendParams &bp, const Task *tasks, const TaskGroup *groups, int n_groups,
                               hipStream_t s);
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
 

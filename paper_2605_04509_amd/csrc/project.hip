@@ -14,14 +14,30 @@
 // Gaussian) whose boxes miss the panel in every view of the cluster gets the
 // "invalid" depth key and no record: it sorts last and is never binned.
 //
-// Arithmetic is IEEE double with FMA contraction disabled (the library is
-// built with -ffp-contract=off); results are rounded to float32 once, when
-// stored.  The evaluation order of every expression is fixed (it is spelled
-// out in the comments) so that two correct implementations of these
-// formulas round to the same float32 values.
+// Arithmetic is double precision with FMA contraction disabled (the library
+// is built with -ffp-contract=off); results are rounded to float32 once, when
+// stored.  The evaluation order of every expression is fixed, and quotients
+// by the depth, the determinant, the conic's last pivot and the direction's
+// norm are taken as products with a reciprocal accurate to about one double
+// ulp (recip below), so the stored float32 values equal those of the plain
+// double formulas except where the exact value lies within a few double ulps
+// of a float32 rounding boundary (about one value in 10^8).  The tile-box
+// extents, which only need to be conservative, are computed in float32.
 #include "lfr_internal.h"
 
 namespace lfr {
+
+// 1/x for the finite, positive, normal x it is used on (depths beyond the
+// near plane, determinants and pivots of the dilated covariance, direction
+// norms): the hardware reciprocal estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 struct Cov3 {
     double xx, xy, xz, yy, yz, zz;
@@ -96,18 +112,19 @@ __device__ inline void sh_colour(const float *shc, double x, double y, double z,
         }
     }
     constexpr int NB = (DEG + 1) * (DEG + 1);
+    // the dot product with fused multiply-adds (one rounding per term)
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
         double acc = 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc = acc + Y[b] * (double)shc[b * 3 + u];
+        for (int b = 0; b < NB; ++b) acc = fma(Y[b], (double)shc[b * 3 + u], acc);
         acc = acc + 0.5;
         col[u] = (float)(acc > 0.0 ? acc : 0.0);
     }
 }
 
 struct MeanProj {
-    double tx, ty, tz, ux, uy;
+    double tx, ty, tz, iz, ux, uy;   // iz = 1 / tz
     float depth;
     float2 m2d;
     bool valid;  // finite and in front of the near plane
@@ -122,8 +139,9 @@ __device__ inline MeanProj project_mean(const DevCamera &c, double mx, double my
     p.tz = ((c.R[6] * mx + c.R[7] * my) + c.R[8] * mz) + c.t[2];
     p.depth = (float)p.tz;
     p.valid = finite && p.depth > kNearZ;
-    p.ux = p.tx / p.tz;
-    p.uy = p.ty / p.tz;
+    p.iz = recip(p.tz);
+    p.ux = p.tx * p.iz;
+    p.uy = p.ty * p.iz;
     p.m2d = make_float2((float)(c.fx * p.ux + c.cx), (float)(c.fy * p.uy + c.cy));
     p.valid = p.valid && isfinite(p.m2d.x) && isfinite(p.m2d.y);
     return p;
@@ -140,9 +158,11 @@ struct FullProj {
 // direction, +0.3 dilation), its inverse in LDL^T form pre-scaled by
 // log2(e)/2, SH colour along camera->mean, and conservative half extents of
 // the region where alpha can reach 1/255.
+// tau_o: the squared-Mahalanobis cutoff 2 ln(255 o) + 0.01 of the Gaussian
+// (cutoff_tau).
 template <int DEG>
 __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, const Cov3 &S,
-                                        double mx, double my, double mz, float o, const float *shc)
+                                        double mx, double my, double mz, float tau_o, const float *shc)
 {
     FullProj f = {};
     const double *R = c.R;
@@ -167,8 +187,8 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
     const double v22 = (a20 * R[6] + a21 * R[7]) + a22 * R[8];
     const double cxl = m.ux < -c.limx ? -c.limx : (m.ux > c.limx ? c.limx : m.ux);
     const double cyl = m.uy < -c.limy ? -c.limy : (m.uy > c.limy ? c.limy : m.uy);
-    const double j00 = c.fx / m.tz, j02 = -(c.fx * cxl) / m.tz;
-    const double j11 = c.fy / m.tz, j12 = -(c.fy * cyl) / m.tz;
+    const double j00 = c.fx * m.iz, j02 = -(c.fx * cxl) * m.iz;
+    const double j11 = c.fy * m.iz, j12 = -(c.fy * cyl) * m.iz;
     const double k00 = j00 * v00 + j02 * v20;
     const double k01 = j00 * v01 + j02 * v21;
     const double k02 = j00 * v02 + j02 * v22;
@@ -179,16 +199,17 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
     const double sc = (k11 * j11 + k12 * j12) + kDilation;
     const double det = sa * sc - sb * sb;
     if (!(det > 0.0)) return f;
-    const double A = sc / det, beta = -sb / sc, G = 1.0 / sc;
+    const double rsc = recip(sc);
+    const double A = sc * recip(det), beta = -sb * rsc, G = rsc;
     f.conic[0] = (float)(A * kHalfLog2e);
     f.conic[1] = (float)beta;
     f.conic[2] = (float)(G * kHalfLog2e);
     // colour
     double dx = mx - c.campos[0], dy = my - c.campos[1], dz = mz - c.campos[2];
-    const double dn = sqrt((dx * dx + dy * dy) + dz * dz);
-    dx = dx / dn;
-    dy = dy / dn;
-    dz = dz / dn;
+    const double rdn = recip(sqrt((dx * dx + dy * dy) + dz * dz));
+    dx = dx * rdn;
+    dy = dy * rdn;
+    dz = dz * rdn;
     sh_colour<DEG>(shc, dx, dy, dz, f.colour);
     bool ok = true;
 #pragma unroll
@@ -196,16 +217,22 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
     ok = ok && f.conic[0] > 0.0f && f.conic[2] > 0.0f;
     if (!ok) return f;
     // Extents of {d : o 2^-E(d) >= 1/255}, i.e. d^T Sigma^-1 d <= tau with
-    // tau = 2 ln(255 o), for the float32 conic actually stored, with margins
-    // that dominate the float32 evaluation error of the blend.
-    double tau = 2.0 * log(255.0 * (double)o);
-    tau = (tau > 0.0 ? tau : 0.0) + 0.01;
-    const double Ar = (double)f.conic[0] / kHalfLog2e, br = (double)f.conic[1],
-                 Gr = (double)f.conic[2] / kHalfLog2e;
-    const double S00 = 1.0 / Ar + br * br / Gr, S11 = 1.0 / Gr;
-    f.ext = make_float2((float)(sqrt(tau * S00) * 1.0001 + 0.02), (float)(sqrt(tau * S11) * 1.0001 + 0.02));
+    // tau = 2 ln(255 o) (tau_o: per Gaussian, + 0.01), for the float32 conic
+    // actually stored, with margins (x 1.0001 + 0.02 px) that dominate both
+    // the float32 evaluation error here and that of the blend.
+    constexpr float kInvHalfLog2e = (float)(1.0 / kHalfLog2e);
+    const float Ar = f.conic[0] * kInvHalfLog2e, br = f.conic[1], Gr = f.conic[2] * kInvHalfLog2e;
+    const float S00 = 1.0f / Ar + br * br / Gr, S11 = 1.0f / Gr;
+    f.ext = make_float2(sqrtf(tau_o * S00) * 1.0001f + 0.02f, sqrtf(tau_o * S11) * 1.0001f + 0.02f);
     f.valid = isfinite(f.ext.x) && isfinite(f.ext.y);
     return f;
+}
+
+// 2 ln(255 o) + 0.01 (0.01 for o <= 1/255): the extents' cutoff.
+__device__ inline float cutoff_tau(float o)
+{
+    const double tau = 2.0 * log(255.0 * (double)o);
+    return (float)((tau > 0.0 ? tau : 0.0) + 0.01);
 }
 
 struct GaussIn {
@@ -261,30 +288,30 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
 constexpr int kProjBlock = 256;
 
 // Store of the 64 lanes' records (Q pieces of 16 bytes each), consecutive in
-// memory from dst, as Q stores of 1 KB each: in store j, lane l writes piece
-// l % Q of record j * (64 / Q) + l / Q, fetched from that record's lane by lane
-// exchanges.  Each store then fills whole cache lines, where a per-lane
-// record store would write 16 bytes into each of 64 lines.
+// memory from dst, as Q stores of 1 KB each, through the wavefront's 1 KB
+// LDS buffer: in round j the 64 / Q lanes whose records the round covers
+// put them into the buffer, then every lane stores the buffer's 16-byte
+// piece `lane`.  Each store fills whole cache lines, where a per-lane
+// record store would write 16 bytes into each of 64 lines.  The buffer is
+// private to the wavefront; the wavefront-scope fences keep the compiler
+// from moving a round's buffer writes across the previous round's reads (a
+// wavefront's LDS accesses are performed in program order).
 template <int Q>
-__device__ __forceinline__ void wave_store(uint4 *dst, const uint4 (&pc)[Q], int lane)
+__device__ __forceinline__ void wave_store(uint4 *dst, const uint4 (&pc)[Q], int lane, uint4 *buf)
 {
+    constexpr int R = 64 / Q;  // records per round
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const int src = j * (64 / Q) + lane / Q;
-        const int which = lane % Q;
-        uint32_t o[4];
+        const int rl = lane - j * R;
+        if (rl >= 0 && rl < R) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            uint32_t v = 0u;
-#pragma unroll
-            for (int p = 0; p < Q; ++p) {
-                const uint32_t w = t == 0 ? pc[p].x : (t == 1 ? pc[p].y : (t == 2 ? pc[p].z : pc[p].w));
-                const uint32_t got = (uint32_t)__shfl((int)w, src, 64);
-                v = which == p ? got : v;
-            }
-            o[t] = v;
+            for (int p = 0; p < Q; ++p) buf[rl * Q + p] = pc[p];
         }
-        dst[j * 64 + lane] = make_uint4(o[0], o[1], o[2], o[3]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        dst[j * 64 + lane] = buf[lane];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -296,6 +323,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     constexpr int NS = (DEG + 1) * (DEG + 1) * 3;  // SH floats per Gaussian
     constexpr int PITCH = NS | 1;
     __shared__ float s_sh[kProjBlock * PITCH];
+    __shared__ uint4 s_stage[kProjBlock / 64][64];  // each wavefront's record-store buffer
     const int64_t i0 = (int64_t)blockIdx.x * kProjBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t M = sc.M, Mp = out.Mp;
@@ -321,7 +349,6 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     float *shc = s_sh + threadIdx.x * PITCH;
     load_gaussian<DEG>(sc, i, g, shc, false);
     const double mx = g.mu[0], my = g.mu[1], mz = g.mu[2];
-    const float nanf_ = __builtin_nanf("");
     // all 64 Gaussians of this wavefront exist: its records are written with
     // whole-wavefront stores (also those of pairs that are not binned, which
     // nothing reads)
@@ -330,11 +357,14 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     const bool want_cov = g.finite && g.o >= kAlphaMin;
     Cov3 S = {};
     if (want_cov) S = cov3d(g.ls, g.q);
+    // per-Gaussian cutoffs: of the extents and of the blend (log2(255 o) + 0.01)
+    const float tau_o = cutoff_tau(g.o);
+    const float ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
     for (int k = 0; k < n_clusters; ++k) {
         const DevCamera &c = cams[cluster_cam[k]];
         const MeanProj m = project_mean(c, mx, my, mz, g.finite);
         FullProj f = {};
-        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, g.o, shc);
+        if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, tau_o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
         // the cluster's views: mean planes, and the union of the tile boxes
@@ -348,7 +378,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
         for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
             const MeanProj mj = project_mean(cams[tg.cv_cam[v]], mx, my, mz, g.finite);
-            const float2 m2 = mj.valid ? mj.m2d : make_float2(nanf_, nanf_);
+            const float2 m2 = mj.valid ? mj.m2d : make_float2(kFarMean, kFarMean);
             out.mean2d[(int64_t)tg.cv_list[v] * M + i] = m2;
             ushort4 b;
             if (!f.valid || !mj.valid || !tile_box(m2, f.ext, tg, b)) continue;
@@ -365,7 +395,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         ItemRec it;
         it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
         it.flags = nv > kItemViews ? 1 : 0;
-        it.ecut = (float)(log2(255.0 * (double)g.o) + 0.01);
+        it.ecut = ecut;
         it.bbox = make_ushort4(x0, x1, y0, y1);
         it.a = f.conic[0];
         it.beta = f.conic[1];
@@ -380,8 +410,9 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
             uint4 ip[4], rp[2];
             __builtin_memcpy(ip, &it, sizeof(ItemRec));
             __builtin_memcpy(rp, &r, sizeof(GaussRec));
-            wave_store<4>(reinterpret_cast<uint4 *>(out.items + (idx - lane)), ip, lane);
-            wave_store<2>(reinterpret_cast<uint4 *>(out.rec + (idx - lane)), rp, lane);
+            uint4 *buf = s_stage[threadIdx.x >> 6];
+            wave_store<4>(reinterpret_cast<uint4 *>(out.items + (idx - lane)), ip, lane, buf);
+            wave_store<2>(reinterpret_cast<uint4 *>(out.rec + (idx - lane)), rp, lane, buf);
             out.ibox[idx] = it.bbox;
         } else if (binned) {
             out.items[idx] = it;
@@ -415,7 +446,7 @@ __global__ void __launch_bounds__(256) project_records_kernel(SceneDev sc, const
     for (int k = 0; k < 3; ++k) r.conic[k] = r.color[k] = 0.0f;
     if (m.valid && g.o >= kAlphaMin) {
         const Cov3 S = cov3d(g.ls, g.q);
-        const FullProj f = project_full<DEG>(*cam, m, S, mx, my, mz, g.o, shc);
+        const FullProj f = project_full<DEG>(*cam, m, S, mx, my, mz, cutoff_tau(g.o), shc);
         if (f.valid) {
             for (int k = 0; k < 3; ++k) {
                 r.conic[k] = f.conic[k];

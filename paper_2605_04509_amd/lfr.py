@@ -72,7 +72,9 @@ class lfr_stats(Structure):
                 ("ms_sort_scatter", c_float), ("sort_scatter_launches", c_int32), ("blend_launches", c_int32),
                 ("ms_bwd_blend", c_float), ("ms_bwd_project", c_float), ("ms_bwd_total", c_float),
                 ("batch_frames", c_int32), ("batch_unplanned", c_int32), ("batch_graphs", c_int32),
-                ("batch_rerendered", c_int32), ("wave_steps", c_uint64), ("wave_steps_live", c_uint64)]
+                ("batch_rerendered", c_int32), ("batch_groups", c_int32), ("wave_steps", c_uint64),
+                ("wave_steps_live", c_uint64),
+                ("saved_forward", c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -85,6 +87,7 @@ class lfr_frame(Structure):
 
 LFR_BATCH_GRAPH = 1
 LFR_BATCH_TIGHT_PLANS = 2
+LFR_BATCH_NO_MERGE = 4
 
 
 class lfr_scene_grads(Structure):
@@ -127,7 +130,8 @@ _SIGS = {
     "lfr_make_view_cone": (c_int32, [POINTER(lfr_view_cone), _P]),
     "lfr_render": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32, POINTER(lfr_render_opts), _P]),
     "lfr_render_batch": (c_int32, [c_void_p, POINTER(lfr_frame), c_int32, c_uint32]),
-    "lfr_render_backward": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, POINTER(lfr_scene_grads)]),
+    "lfr_render_backward": (c_int32, [c_void_p, c_uint64, c_void_p, POINTER(lfr_scene), _P,
+                                      POINTER(lfr_scene_grads)]),
     "lfr_render_fullframe_interlace": (c_int32, [c_void_p, c_void_p, POINTER(lfr_scene), _P, c_int32,
                                                  POINTER(lfr_render_opts), c_int32, _P]),
     "lfr_project": (c_int32, [c_void_p, POINTER(lfr_scene), _P, c_int32, c_int32, _P]),
@@ -384,30 +388,37 @@ class Frame:
         self.cams = cams if isinstance(cams, ctypes.Array) else cameras_array(cams)
 
 
-def render_batch(ctx: Context, frames, graph=True, tight_plans=False):
+def render_batch(ctx: Context, frames, graph=True, tight_plans=False, merge=True):
     """Render a list of :class:`Frame` with lfr_render_batch (one host
-    synchronization at the end; planned frames replayed from hipGraphs with
-    ``graph``).  Returns the batch counters of lfr_stats."""
+    synchronization at the end; planned groups replayed from hipGraphs with
+    ``graph``; consecutive frames sharing display, scene and options merged
+    into one render unless ``merge`` is False).  Returns the batch counters
+    of lfr_stats."""
     n = len(frames)
     scenes = [f.scene.c_struct() for f in frames]          # kept alive for the call
     arr = (lfr_frame * max(n, 1))()
     for i, f in enumerate(frames):
         arr[i] = lfr_frame(f.display.handle.value, ctypes.pointer(scenes[i]), ctypes.addressof(f.cams), len(f.cams),
                            f.opts, f.out.data_ptr())
-    flags = (LFR_BATCH_GRAPH if graph else 0) | (LFR_BATCH_TIGHT_PLANS if tight_plans else 0)
+    flags = ((LFR_BATCH_GRAPH if graph else 0) | (LFR_BATCH_TIGHT_PLANS if tight_plans else 0)
+             | (0 if merge else LFR_BATCH_NO_MERGE))
     _check(library().lfr_render_batch(ctx.handle, arr, n, flags), ctx.handle)
     st = ctx.stats()
-    return {k: st[k] for k in ("batch_frames", "batch_unplanned", "batch_graphs", "batch_rerendered")}
+    return {k: st[k] for k in ("batch_frames", "batch_unplanned", "batch_graphs", "batch_rerendered",
+                               "batch_groups")}
 
 
 GRAD_NAMES = ("means", "log_scales", "quats", "opacities", "sh")
 
 
-def render_backward(ctx: Context, display: Display, scene: DeviceScene, grad_out, grads=None):
+def render_backward(ctx: Context, display: Display, scene: DeviceScene, grad_out, grads=None, saved_forward=0):
     """Gradients of the last ``render(..., save_for_backward=True)`` on
     ``ctx`` for the image gradient ``grad_out`` ([H, W, 3] float32 device).
     Returns a dict of tensors shaped like the scene arrays (``grads`` may
-    supply them; every element is overwritten)."""
+    supply them; every element is overwritten).  ``saved_forward``: the
+    ``stats()["saved_forward"]`` id read after that render (0: whichever
+    forward the context keeps); the library refuses an id it no longer
+    keeps."""
     torch = _torch()
     _require_device_f32(grad_out, "grad_out")
     if tuple(grad_out.shape) != (display.height, display.width, 3):
@@ -420,8 +431,8 @@ def render_backward(ctx: Context, display: Display, scene: DeviceScene, grad_out
             raise ValueError(f"grads[{k}] must have the shape of scene.{k}")
     g = lfr_scene_grads(*(grads[k].data_ptr() for k in GRAD_NAMES))
     sc = scene.c_struct()
-    _check(library().lfr_render_backward(ctx.handle, display.handle, ctypes.byref(sc), _ptr(grad_out),
-                                         ctypes.byref(g)), ctx.handle)
+    _check(library().lfr_render_backward(ctx.handle, int(saved_forward), display.handle, ctypes.byref(sc),
+                                         _ptr(grad_out), ctypes.byref(g)), ctx.handle)
     return grads
 
 
@@ -430,8 +441,10 @@ def _autograd_function():
 
     class RenderFunction(torch.autograd.Function):
         """Forward: lfr_render with LFR_SAVE_FOR_BACKWARD; backward:
-        lfr_render_backward.  The context must not render again before the
-        backward runs (the library refuses with LFR_ERR_INVALID_ARG)."""
+        lfr_render_backward of that forward (its id is recorded).  The
+        context must not render again before the backward runs: the library
+        refuses with LFR_ERR_INVALID_ARG rather than return the gradients of
+        another render."""
 
         @staticmethod
         def forward(fctx, means, log_scales, quats, opacities, sh, ctx, display, cams, sh_degree, cluster_size,
@@ -440,13 +453,13 @@ def _autograd_function():
                                 sh.detach(), sh_degree)
             out = render(ctx, display, scene, cams, cluster_size=cluster_size, remap=remap, cull=cull,
                          background=background, save_for_backward=True)
-            fctx.lfr = (ctx, display, scene)
+            fctx.lfr = (ctx, display, scene, ctx.stats()["saved_forward"])
             return out
 
         @staticmethod
         def backward(fctx, grad_out):
-            ctx, display, scene = fctx.lfr
-            g = render_backward(ctx, display, scene, grad_out.contiguous())
+            ctx, display, scene, saved = fctx.lfr
+            g = render_backward(ctx, display, scene, grad_out.contiguous(), saved_forward=saved)
             return (g["means"], g["log_scales"], g["quats"], g["opacities"], g["sh"],
                     None, None, None, None, None, None, None, None)
 

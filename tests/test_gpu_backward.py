@@ -187,6 +187,54 @@ def test_autograd_function_mse(lib):
     d.close()
 
 
+def test_two_live_forwards_on_one_context_are_refused(lib):
+    """Two differentiable renders on one context before one backward: the
+    context keeps only the second forward's lists, so the first node's
+    backward must be refused (never computed from the other render), and a
+    backward with other scene arrays of the same size too.  On separate
+    contexts the same loss works and matches two forward/backward pairs."""
+    lfr, ctx = lib
+    scene, params, cams_list = grad_subset()
+    cams = pack_cameras(cams_list)
+    cams2 = cams.copy()
+    cams2[:, 9] += 0.05                               # another rig position
+    d = lfr.Display(ctx, params)
+    ds = lfr.DeviceScene.from_numpy(scene, device="cuda:0")
+    say("two forwards, one backward")
+    params_t = [getattr(ds, k).clone().requires_grad_(True) for k in NAMES]
+    a = lfr.render_differentiable(ctx, d, *params_t, 3, cams, cluster_size=1)
+    b = lfr.render_differentiable(ctx, d, *params_t, 3, cams2, cluster_size=1)
+    with pytest.raises(lfr.LfrError) as ei:
+        (a.square().mean() + b.square().mean()).backward()
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    # other arrays with the same M and degree are refused as well
+    lfr.render(ctx, d, ds, cams, cluster_size=1, save_for_backward=True)
+    other = lfr.DeviceScene(ds.means.clone(), ds.log_scales, ds.quats, ds.opacities, ds.sh, 3)
+    g = torch.ones((params.height, params.width, 3), device="cuda:0")
+    with pytest.raises(lfr.LfrError):
+        lfr.render_backward(ctx, d, other, g)
+    # one context per render: both backwards run and add up
+    c1, c2 = lfr.Context(0), lfr.Context(0)
+    d1, d2 = lfr.Display(c1, params), lfr.Display(c2, params)
+    params_t = [getattr(ds, k).clone().requires_grad_(True) for k in NAMES]
+    a = lfr.render_differentiable(c1, d1, *params_t, 3, cams, cluster_size=1)
+    b = lfr.render_differentiable(c2, d2, *params_t, 3, cams2, cluster_size=1)
+    (a.square().mean() + b.square().mean()).backward()
+    want = {k: torch.zeros_like(getattr(ds, k), dtype=torch.float64) for k in NAMES}
+    for cc, dd, cm, img in ((c1, d1, cams, a), (c2, d2, cams2, b)):
+        lfr.render(cc, dd, ds, cm, cluster_size=1, save_for_backward=True)
+        gr = lfr.render_backward(cc, dd, ds, (2.0 * img.detach() / img.numel()).contiguous())
+        for k in NAMES:
+            want[k] += gr[k].double()
+    torch.cuda.synchronize()
+    for k, p in zip(NAMES, params_t):
+        assert torch.linalg.norm(p.grad.double() - want[k]) <= 1e-5 * torch.linalg.norm(want[k]) + 1e-30, k
+    for x in (d, d1, d2):
+        x.close()
+    c1.close()
+    c2.close()
+
+
 def test_backward_error_paths(lib):
     lfr, ctx = lib
     w = get_workload("tiny")
@@ -241,16 +289,19 @@ def test_backward_repeatable_within_atomic_rounding(lib):
     d2.close()
 
 
-def test_backward_display_scale_sampled(lib):
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
+def test_backward_display_scale_sampled(lib, tile):
     """The 200k-Gaussian, 45-view, 1920x1080 scene (the backward benchmark
-    configuration) at cluster size 1: the image gradient is non-zero on
-    1500 sampled subpixels only, so the oracle's gradient (a sum over those
-    subpixels) is computable on the CPU."""
+    configuration) at cluster size 1, on the tile shapes the benchmark picks
+    from: the image gradient is non-zero on 1500 sampled subpixels only, so
+    the oracle's gradient (a sum over those subpixels) is computable on the
+    CPU."""
     lfr, ctx = lib
     w = get_workload("display")
     scene = w.make_scene()
     cams = pack_cameras(w.cameras())
-    p = w.display.with_tile(16, 16)
+    p = w.display.with_tile(*tile)
     n = 3 * p.width * p.height
     rng = np.random.Generator(np.random.PCG64(77))
     samples = np.sort(rng.choice(n, 1500, replace=False))

@@ -80,23 +80,27 @@ def _check_equal(frames, refs):
         assert torch.equal(f.out, r), f"frame {i} differs"
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_matches_individual_renders(lib, graph):
+@pytest.mark.parametrize("graph,merge", [(True, True), (False, True), (True, False), (False, False)])
+def test_batch_matches_individual_renders(lib, graph, merge):
+    """Merged groups: the three poses of each of the first two panels (same
+    display, scene and options, remapped blend) render as one group each;
+    the third panel's frames (row-major blend) render one by one."""
     lfr, ctx = lib
     bctx = lfr.Context(0)
     frames, ref_args, displays, scenes = _setup(lfr, ctx)
     refs = _reference(lfr, ctx, frames, ref_args)
     n = len(frames)
-    say("batch of", n, "frames, graph", graph)
-    st = lfr.render_batch(bctx, frames, graph=graph)
+    say("batch of", n, "frames, graph", graph, "merge", merge)
+    st = lfr.render_batch(bctx, frames, graph=graph, merge=merge)
     torch.cuda.synchronize()
     assert st["batch_frames"] == n and st["batch_unplanned"] == n
+    assert st["batch_groups"] == (5 if merge else n)
     _check_equal(frames, refs)
     seen_graphs = 0
     for rep in range(3):
         for f in frames:
             f.out.zero_()
-        st = lfr.render_batch(bctx, frames, graph=graph)
+        st = lfr.render_batch(bctx, frames, graph=graph, merge=merge)
         torch.cuda.synchronize()
         say(" repeat", rep, st)
         assert st["batch_unplanned"] == 0
@@ -112,7 +116,7 @@ def test_batch_matches_individual_renders(lib, graph):
         f.set_cameras(_rig(p, tuple(rng.uniform(-0.05, 0.05, 3))))
         f.out.zero_()
     refs = _reference(lfr, ctx, frames, ref_args)
-    st = lfr.render_batch(bctx, frames, graph=graph)
+    st = lfr.render_batch(bctx, frames, graph=graph, merge=merge)
     torch.cuda.synchronize()
     say(" new poses", st)
     assert st["batch_unplanned"] == 0
@@ -163,12 +167,67 @@ def test_batch_frame_against_oracle(lib):
     rng = np.random.Generator(np.random.PCG64(5))
     samples = np.sort(rng.choice(V.size, 3000, replace=False))
     cams = np.frombuffer(bytes(f.cams), dtype=np.float32).reshape(-1, 16)
-    ref, flags, tflag = oracle.render_subpixels(sc, cams, p, V, S, samples)
+    r = oracle.render_subpixels_ranged(sc, cams, p, V, S, samples)
     got = f.out.cpu().numpy().reshape(-1)[samples]
     say("batch frame vs oracle, S", S)
-    compare(got, ref, flags, tflag, colour_bound(sc), label='batch frame')
+    say(compare(got, r, colour_bound(sc), label='batch frame'))
     bctx.close()
     for d in displays:
+        d.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("S", [8])
+def test_full_size_serving_batch_against_oracle(lib, S):
+    """The serving configuration at full size: three outdoor-style scenes
+    (0.5M / 1M / 3M Gaussians) on 1920x1080/45-view, 2560x1440/64-view and
+    3840x2160/100-view panels, two head poses each, on 32x64 tiles, rendered
+    by lfr_render_batch (planned, replayed from captured graphs).  Every
+    frame equals lfr_render's image; one frame of each panel is checked
+    against the oracle on about 1024 subpixels spread over all its views."""
+    from workloads.configs import batched_frames
+    lfr, ctx = lib
+    bctx = lfr.Context(0)
+    frames, refs, keep = [], [], []
+    for seed_i, m, disp, radius, span, offs in batched_frames(num_poses=2):
+        say("panel", disp.width, disp.height, disp.num_views, "scene", seed_i, m)
+        sc = mixture_scene(seed_i, m, 3)
+        ds = lfr.DeviceScene.from_numpy(sc, device="cuda:0")
+        d = lfr.Display(ctx, disp.with_tile(32, 64))
+        keep.append((d, ds, sc, disp, radius, span))
+        for o in offs:
+            cams = pack_cameras(orbit_rig(disp.num_views, disp.width, disp.height, radius, span, 60.0,
+                                          centre=(0.0, 0.0, radius), rig_offset=tuple(o)))
+            out = torch.zeros((disp.height, disp.width, 3), device="cuda:0")
+            frames.append(lfr.Frame(d, ds, cams, out, cluster_size=S))
+            refs.append((len(keep) - 1, cams))
+    for rep in range(3):
+        st = lfr.render_batch(bctx, frames, graph=True)
+        torch.cuda.synchronize()
+        say(" batch", rep, st)
+    assert st["batch_unplanned"] == 0
+    assert st["batch_groups"] == 3              # the two poses of each panel merge
+    for i, (f, (k, cams)) in enumerate(zip(frames, refs)):
+        d, ds, sc, disp, radius, span = keep[k]
+        one = lfr.render(ctx, d, ds, cams, cluster_size=S)
+        torch.cuda.synchronize()
+        assert torch.equal(one, f.out), f"frame {i} differs from lfr_render"
+        del one
+    for k, (d, ds, sc, disp, radius, span) in enumerate(keep):
+        i = 2 * k + 1                               # the second pose of each panel
+        f, cams = frames[i], refs[i][1]
+        V = oracle.view_map(disp)
+        views = np.unique(V)
+        rng = np.random.default_rng(k)
+        flat = V.reshape(-1)
+        samples = np.sort(np.concatenate([rng.choice(np.flatnonzero(flat == j), -(-1024 // len(views)),
+                                                     replace=False) for j in views]))
+        with oracle.threads():
+            r = oracle.render_subpixels_ranged(sc, cams, disp, V, S, samples)
+        got = f.out.cpu().numpy().reshape(-1)[samples]
+        say(" panel", disp.width, disp.height, compare(got, r, colour_bound(sc), label=f"batch panel {k}"))
+    bctx.close()
+    for d, *_ in keep:
         d.close()
 
 

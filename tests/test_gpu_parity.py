@@ -191,8 +191,9 @@ def test_tiny_full_frame_parity(lib, tiny_setup, S):
     say("tiny full frame S =", S)
     d = _display(lfr, ctx, w.display)
     img = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=True)
-    ref, flags, tflag = oracle.render_frame(scene, cams, w.display, V, S)
-    info = compare(img, ref, flags, tflag, colour_bound(scene), label=f"tiny S={S}")
+    with oracle.threads():
+        r = oracle.render_frame_ranged(scene, cams, w.display, V, S)
+    info = compare(img, r, colour_bound(scene), label=f"tiny S={S}")
     say(info)
     # remap changes only the thread order, never a value
     img2 = _render(lfr, ctx, d, ds, cams, cluster_size=S, remap=False)
@@ -311,9 +312,8 @@ def test_ragged_panel_and_background(lib):
             img = _render(lfr, ctx, d, ds, cams, cluster_size=S, background=bg)
             rng = np.random.default_rng(S)
             samples = rng.choice(V.size, 4000, replace=False)
-            ref, flags, tflag = oracle.render_subpixels(scene, cams, p, V, S, samples, bg)
-            compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene) + 1.0,
-                    label=f"ragged {tile} S={S}")
+            r = oracle.render_subpixels_ranged(scene, cams, p, V, S, samples, bg)
+            say(compare(img.reshape(-1)[samples], r, colour_bound(scene) + 1.0, label=f"ragged {tile} S={S}"))
         d.close()
 
 
@@ -340,8 +340,8 @@ def test_degenerate_scenes(lib):
     V = oracle.view_map(p)
     for S in (1, 8):
         img = _render(lfr, ctx, d, lfr.DeviceScene.from_numpy(one), cams, cluster_size=S, background=bg)
-        ref, flags, tflag = oracle.render_frame(one, cams, p, V, S, bg)
-        compare(img, ref, flags, tflag, 2.0, label=f"one S={S}")
+        r = oracle.render_frame_ranged(one, cams, p, V, S, bg)
+        compare(img, r, 2.0, label=f"one S={S}")
     d.close()
 
 
@@ -396,6 +396,13 @@ def _sample_in_views(V, views, per_view, seed):
     return np.sort(np.concatenate(out))
 
 
+def _sample_every_view(V, total, seed):
+    """About `total` subpixels spread evenly over every view the panel uses
+    (so over every cluster, the padded last one included)."""
+    views = np.unique(V)
+    return _sample_in_views(V, views, -(-total // len(views)), seed), views
+
+
 @pytest.mark.parametrize("S", [1, 8])
 def test_display_workload_sampled(lib, S):
     lfr, ctx = lib
@@ -404,14 +411,14 @@ def test_display_workload_sampled(lib, S):
     scene = w.make_scene()
     cams = pack_cameras(w.cameras())
     V = oracle.view_map(w.display)
-    d = _display(lfr, ctx, w.display)
+    d = _display(lfr, ctx, w.display.with_tile(32, 32))
     ds = lfr.DeviceScene.from_numpy(scene)
     img = _render(lfr, ctx, d, ds, cams, cluster_size=S)
-    views = [0, 22] if S == 1 else [18, 22]          # S = 8: both in cluster 2 (rep 20)
-    samples = _sample_in_views(V, views, 600, S)
-    ref, flags, tflag = oracle.render_subpixels(scene, cams, w.display, V, S, samples)
-    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), label=f"display S={S}")
-    say(info)
+    samples, views = _sample_every_view(V, 2048, S)
+    with oracle.threads():
+        r = oracle.render_subpixels_ranged(scene, cams, w.display, V, S, samples)
+    info = compare(img.reshape(-1)[samples], r, colour_bound(scene), label=f"display S={S}")
+    say(len(views), "views", info)
     if S == 1:
         ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=10)
         torch.cuda.synchronize()
@@ -419,63 +426,92 @@ def test_display_workload_sampled(lib, S):
     d.close()
 
 
-def test_outdoor_workload_bench_configuration(lib):
-    """3M Gaussians, 100 views, 3840x2160, cluster size 8, remap on: the
-    configuration the benchmark times, checked on sampled subpixels."""
-    lfr, ctx = lib
+# the tile shapes the benchmark's autotuner chooses among
+BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64))
+
+
+@pytest.fixture(scope="module")
+def outdoor(lib):
     w = get_workload("outdoor")
-    say("outdoor workload (3M Gaussians, 4K, 100 views) S = 8")
+    say("generating the outdoor scene (3M Gaussians)")
     scene = w.make_scene()
     cams = pack_cameras(w.cameras())
     V = oracle.view_map(w.display)
-    d = _display(lfr, ctx, w.display)
+    return w, scene, cams, V
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("S,n_samples", [(8, 4096), (1, 1024)])
+def test_outdoor_workload_bench_configuration(lib, outdoor, S, n_samples):
+    """3M Gaussians, 100 views, 3840x2160, remap on, default depth chunks:
+    the frame the benchmark times (cluster size 8) and its exact-path
+    ablation (cluster size 1).  The image is rendered on every tile shape the
+    autotuner picks from and must be bit-identical across them; subpixels
+    spread over all 31 views the panel uses (all clusters, the padded last
+    one included) are checked against the oracle."""
+    lfr, ctx = lib
+    w, scene, cams, V = outdoor
     ds = lfr.DeviceScene.from_numpy(scene)
-    img = _render(lfr, ctx, d, ds, cams, cluster_size=8)
-    st = ctx.stats()
-    say(st)
-    samples = _sample_in_views(V, [48, 51], 100, 3)   # cluster 6 (views 48..55, rep 52)
-    ref, flags, tflag = oracle.render_subpixels(scene, cams, w.display, V, 8, samples)
-    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
-                   label="outdoor S=8")
-    say(info)
+    imgs = {}
+    for tile in BENCH_TILES:
+        say("outdoor S =", S, "tile", tile)
+        d = _display(lfr, ctx, w.display.with_tile(*tile))
+        imgs[tile] = _render(lfr, ctx, d, ds, cams, cluster_size=S)
+        st = ctx.stats()
+        say(" pairs", st["pairs"], "chunks", st["chunks"], "clusters", st["clusters"])
+        assert st["chunks"] > 1
+        d.close()
+    img = imgs[(32, 64)]
+    for tile, im in imgs.items():
+        np.testing.assert_array_equal(im, img, err_msg=f"tile {tile}")
     assert np.isfinite(img).all()
-    d.close()
+    samples, views = _sample_every_view(V, n_samples, 3)
+    if S == 8:
+        assert len(views) == 31 and {int(v) // 8 for v in views} == set(range(13))
+        assert any(v >= 96 for v in views)            # the padded last cluster
+    say(f"oracle on {samples.size} subpixels of {len(views)} views")
+    with oracle.threads():
+        r = oracle.render_subpixels_ranged(scene, cams, w.display, V, S, samples)
+    info = compare(img.reshape(-1)[samples], r, colour_bound(scene), label=f"outdoor S={S}")
+    say(info)
 
 
-@pytest.mark.parametrize("name,S,views", [("landscape71", 18, [19, 27]), ("portrait63", 16, [33, 40])])
-def test_paper_display_shapes(lib, name, S, views):
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,S", [("landscape71", 18), ("portrait63", 16)])
+def test_paper_display_shapes(lib, outdoor, name, S):
     """The paper's two display shapes (71 views over 53 degrees at 3840x2160
     with reuse groups of 18; 63 views over 53 degrees at 1440x2560 with groups
-    of 16, the last group padded) on the 3M-Gaussian scene: sampled subpixels
-    of two views of one cluster against the oracle, and the exact path's
-    image against full-frame-then-interlace on the same display."""
+    of 16, the last group padded) on the 3M-Gaussian scene, on the tile shapes
+    the benchmark picks (64x32 and 32x64, bit-identical): subpixels spread
+    over every view against the oracle, and the exact path's image against
+    full-frame-then-interlace on the same display."""
     lfr, ctx = lib
     w = get_workload(name)
-    say(name, "S =", S, "views", views)
-    scene = w.make_scene()
+    say(name, "S =", S)
+    scene = outdoor[1]
     cams = pack_cameras(w.cameras())
     V = oracle.view_map(w.display)
     assert len(np.unique(V)) == w.display.num_views
-    params = w.display.with_tile(32, 32)
-    d = _display(lfr, ctx, params)
     ds = lfr.DeviceScene.from_numpy(scene)
-    img = _render(lfr, ctx, d, ds, cams, cluster_size=S)
-    samples = _sample_in_views(V, views, 100, 3)
-    ref, flags, tflag = oracle.render_subpixels(scene, cams, params, V, S, samples)
-    info = compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
-                   label=f"{name} S={S}")
+    imgs = {}
+    for tile in ((64, 32), (32, 64)):
+        d = _display(lfr, ctx, w.display.with_tile(*tile))
+        imgs[tile] = _render(lfr, ctx, d, ds, cams, cluster_size=S)
+        say(" tile", tile, ctx.stats()["pairs"], "pairs")
+        if tile == (64, 32):
+            exact = _render(lfr, ctx, d, ds, cams, cluster_size=1)
+            ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=18, tile=32)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(ff.cpu().numpy(), exact)
+        d.close()
+    np.testing.assert_array_equal(imgs[(64, 32)], imgs[(32, 64)])
+    img = imgs[(64, 32)]
+    samples, views = _sample_every_view(V, 2048, 3)
+    assert w.display.num_views - 1 in views            # the padded last cluster
+    with oracle.threads():
+        r = oracle.render_subpixels_ranged(scene, cams, w.display, V, S, samples)
+    info = compare(img.reshape(-1)[samples], r, colour_bound(scene), label=f"{name} S={S}")
     say(info)
-    # the last cluster is padded with the last view: its subpixels too
-    last = [w.display.num_views - 1]
-    samples = _sample_in_views(V, last, 60, 3)
-    ref, flags, tflag = oracle.render_subpixels(scene, cams, params, V, S, samples)
-    compare(img.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), max_flag_frac=0.02,
-            label=f"{name} S={S} padded cluster")
-    exact = _render(lfr, ctx, d, ds, cams, cluster_size=1)
-    ff = lfr.render_fullframe_interlace(ctx, d, ds, cams, view_batch=18, tile=32)
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(ff.cpu().numpy(), exact)
-    d.close()
 
 
 def test_elongated_splats_cull_exactly(lib):
@@ -511,6 +547,6 @@ def test_elongated_splats_cull_exactly(lib):
             torch.cuda.synchronize()
             np.testing.assert_array_equal(ff.cpu().numpy(), a)
         samples = np.sort(np.random.default_rng(S).choice(V.size, 4000, replace=False))
-        ref, flags, tflag = oracle.render_subpixels(scene, cams, p, V, S, samples)
-        say(compare(a.reshape(-1)[samples], ref, flags, tflag, colour_bound(scene), label=f"elongated S={S}"))
+        r = oracle.render_subpixels_ranged(scene, cams, p, V, S, samples)
+        say(compare(a.reshape(-1)[samples], r, colour_bound(scene), label=f"elongated S={S}"))
     d.close()
