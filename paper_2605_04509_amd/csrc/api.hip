@@ -602,53 +602,6 @@ lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, in
     return LFR_OK;
 }
 
-// Workgroups of the blend: runs of consecutive work items of one (tile,
-// cluster) list (consecutive after ordering), at most kGroupTasks items
-// with at most kGroupViews distinct views between them.
-std::vector<TaskGroup> group_tasks(const std::vector<Task> &h)
-{
-    std::vector<TaskGroup> g;
-    for (size_t e = 0; e < h.size(); ++e) {
-        const Task &t = h[e];
-        bool join = !g.empty();
-        if (join) {
-            const TaskGroup &c = g.back();
-            const Task &f = h[c.first];
-            join = f.tile == t.tile && f.cluster == t.cluster && c.n_tasks < kGroupTasks;
-            int extra = 0;
-            for (int q = 0; q < (int)t.n_runs && join; ++q) {
-                bool seen = false;
-                for (int v = 0; v < (int)c.n_views; ++v) seen = seen || c.slot[v] == t.slot[q];
-                for (int r = 0; r < q; ++r) seen = seen || t.slot[r] == t.slot[q];
-                extra += seen ? 0 : 1;
-            }
-            join = join && (int)c.n_views + extra <= kGroupViews;
-        }
-        if (!join) {
-            TaskGroup ng{};
-            ng.first = (uint32_t)e;
-            g.push_back(ng);
-        }
-        TaskGroup &c = g.back();
-        ++c.n_tasks;
-        for (int q = 0; q < (int)t.n_runs; ++q) {
-            bool seen = false;
-            for (int v = 0; v < (int)c.n_views; ++v) seen = seen || c.slot[v] == t.slot[q];
-            if (!seen) c.slot[c.n_views++] = t.slot[q];
-        }
-    }
-    return g;
-}
-
-lfr_status upload_groups(lfr_context *ctx, const std::vector<TaskGroup> &g, TaskSet *ts)
-{
-    ts->n_groups = (int)g.size();
-    HIPCHK(ctx, hipMalloc((void **)&ts->d_groups, sizeof(TaskGroup) * std::max<size_t>(g.size(), 1)));
-    if (!g.empty())
-        HIPCHK(ctx, hipMemcpy(ts->d_groups, g.data(), sizeof(TaskGroup) * g.size(), hipMemcpyHostToDevice));
-    return LFR_OK;
-}
-
 // Blend work items and per-(tile, cluster) subpixel counts for cluster
 // size S, built once per display.
 lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
@@ -708,11 +661,6 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
     ts.n = (int)n;
     std::vector<Task> h;
     CHK(order_tasks(ctx, d, ts.d_tasks, ts.n, &h));
-    {
-        const lfr_status gs = upload_groups(ctx, group_tasks(h), &ts);
-        if (ts.d_groups) guard.owned.push_back(ts.d_groups);
-        CHK(gs);
-    }
     guard.keep = true;
     auto ins = d->tasks.emplace(key, ts);
     *out = &ins.first->second;
@@ -758,17 +706,6 @@ lfr_status get_group_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, 
         for (int64_t t = 0; t < d->T; ++t)
             for (int k = 0; k < K; ++k) cg[(size_t)(t << cbg) | (size_t)(f * K + k)] = c1[(size_t)(t << cb1) | k];
     }
-    std::vector<TaskGroup> g1(std::max(base->n_groups, 1));
-    if (base->n_groups)
-        HIPCHK(ctx, hipMemcpy(g1.data(), base->d_groups, sizeof(TaskGroup) * base->n_groups, hipMemcpyDeviceToHost));
-    std::vector<TaskGroup> gg;
-    for (int f = 0; f < F; ++f)
-        for (int e = 0; e < base->n_groups; ++e) {
-            TaskGroup t = g1[e];
-            t.first += (uint32_t)(f * base->n);
-            for (int v = 0; v < (int)t.n_views; ++v) t.slot[v] = (uint16_t)(t.slot[v] + f * NV);
-            gg.push_back(t);
-        }
     TaskSet ts;
     ts.cluster_bits = cbg;
     ts.n = F * base->n;
@@ -787,11 +724,6 @@ lfr_status get_group_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, 
     guard.p.push_back(ts.d_tc_count);
     if (!hg.empty()) HIPCHK(ctx, hipMemcpy(ts.d_tasks, hg.data(), sizeof(Task) * hg.size(), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ts.d_tc_count, cg.data(), sizeof(uint32_t) * cg.size(), hipMemcpyHostToDevice));
-    {
-        const lfr_status gs = upload_groups(ctx, gg, &ts);
-        if (ts.d_groups) guard.p.push_back(ts.d_groups);
-        CHK(gs);
-    }
     guard.keep = true;
     auto ins = d->tasks.emplace(key, ts);
     *out = &ins.first->second;
@@ -1024,7 +956,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
             bp.last = last ? 1 : 0;
             const size_t e0 = tm.mark(s);
             if (remap)
-                HIPCHK(ctx, launch_blend_group(bp, ts->d_tasks, ts->d_groups, ts->n_groups, s));
+                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
             else
                 HIPCHK(ctx, launch_blend_rowmajor(bp, s));
             const size_t e1 = tm.mark(s);
@@ -1331,7 +1263,6 @@ void lfr_display_destroy(lfr_display *d)
         if (kv.second.d_tasks) (void)hipFree(kv.second.d_tasks);
         if (kv.second.d_view_cluster) (void)hipFree(kv.second.d_view_cluster);
         if (kv.second.d_tc_count) (void)hipFree(kv.second.d_tc_count);
-        if (kv.second.d_groups) (void)hipFree(kv.second.d_groups);
     }
     delete d;
 }

@@ -365,304 +365,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
     }
 }
 
-// The work items of one (tile, cluster) list as one workgroup: one
-// wavefront per item (up to kGroupTasks items, up to kGroupViews distinct
-// views), and every batch of 64 list entries fetched once for all of them,
-// straight into LDS (gfx950's 16-byte global-to-LDS loads: no registers
-// hold the batch in flight).  Fetching is spread over the wavefronts by
-// parts: part 0 is the entries' records (conic and opacity, colour), part
-// 1 + v their means in the group's view v (a 16-byte load whose first 8
-// bytes are the mean); wavefront w issues parts w, w + n, w + 2n, ... (n
-// items).  The next batch's loads are issued before the current batch is
-// walked and land in the other of two LDS buffers.  Every wavefront then
-// culls the staged batch against the sample-centre boxes of its own
-// unfinished lanes (per view run), compacts the entries that can reach one
-// of them into its own index list, and walks them exactly like
-// blend_remap_kernel: the per-lane arithmetic, order and decisions are
-// identical, so the image is bit-identical.  A finished wavefront keeps
-// fetching for the others; the group leaves when all of its wavefronts are
-// done or the list ends.
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) void global_void;
-
-__device__ __forceinline__ void load_to_lds(const void *src, void *lds_base)
-{
-    __builtin_amdgcn_global_load_lds((global_void *)src, (lds_void *)lds_base, 16, 0, 0);
-}
-
-template <bool kCount, bool kSave>
-__global__ void __launch_bounds__(kGroupTasks * kWave) __attribute__((amdgpu_waves_per_eu(6)))
-blend_group_kernel(BlendParams bp, const Task *__restrict__ tasks, const TaskGroup *__restrict__ groups,
-                   int n_groups)
-{
-    constexpr int kPad = kWave;                           // a zero-opacity entry used as padding
-    __shared__ float4 s_a[2][kWave + 1];                  // A', beta, G', o
-    __shared__ float4 s_c[2][kWave + 1];                  // r, g, b, then the cutoff exponent
-    __shared__ float2 s_h[2][kWave + 1];                  // culling half extents
-    __shared__ float4 s_mu[2][kGroupViews][kWave + 1];    // .xy: means in the group's views
-    __shared__ uint8_t s_rel[kGroupTasks][kWave];         // each wavefront's compacted entries
-    __shared__ float4 s_box[kGroupTasks][kMaxWaveViews];  // per view run: unfinished lanes' x0, x1, y0, y1
-    __shared__ uint32_t s_done[kGroupTasks];
-
-    const int gi = xcd_task(blockIdx.x);
-    if (gi >= n_groups) return;
-    const TaskGroup G = groups[gi];
-    const int nt = G.n_tasks, nv = G.n_views;
-    // a later depth chunk: nothing to do when every item of the group is done
-    bool any_alive = bp.first != 0;
-    for (int t = 0; t < nt && !any_alive; ++t) any_alive = bp.task_alive[G.first + t] != 0;
-    if (!any_alive) return;
-    // the wavefront index, known to the compiler as uniform (scalar loads of the item)
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    if (wv >= nt) return;  // (whole wavefronts; the barrier no longer waits for them)
-    const int ti = (int)G.first + wv;
-    const bool task_live = bp.first || bp.task_alive[ti];
-    const Task tk = tasks[ti];
-    const bool active = task_live && lane < (int)tk.count;
-    const uint32_t at = tk.start + (lane < (int)tk.count ? lane : (int)tk.count - 1);
-    const uint32_t p = bp.psi[at];
-    const uint32_t pix = p / 3;
-    const int u = (int)(p - 3 * pix);
-    const uint32_t y = pix / (uint32_t)bp.W;
-    const uint32_t x = pix - y * (uint32_t)bp.W;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const float bgu = bp.bg[u];
-    const int n_runs = tk.n_runs;
-    const int my_run = (lane >= (int)tk.run_start[1]) + (lane >= (int)tk.run_start[2]) + (lane >= (int)tk.run_start[3]);
-    // the group view of each of this item's view runs
-    int gview[kMaxWaveViews];
-#pragma unroll
-    for (int q = 0; q < kMaxWaveViews; ++q) {
-        int g = 0;
-#pragma unroll
-        for (int v = 0; v < kGroupViews; ++v) g = (v < nv && G.slot[v] == tk.slot[q]) ? v : g;
-        gview[q] = g;
-    }
-    const int my_gv = my_run == 0 ? gview[0] : (my_run == 1 ? gview[1] : (my_run == 2 ? gview[2] : gview[3]));
-
-    const uint32_t list = (tk.tile << bp.cluster_bits) | tk.cluster;
-    const uint2 range = bp.ranges[list];
-    const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
-    float *const out = bp.out_frames ? bp.out_frames[tk.frame] : bp.out;
-    float2 *const state = bp.state + (int64_t)tk.frame * bp.n_sub;
-    float T = 1.0f, C = 0.0f;
-    if (!bp.first && active) {
-        const float2 st = state[at];
-        T = st.x;
-        C = st.y;
-    }
-    if (!active) T = 0.0f;
-    const bool was_done = T == 0.0f;
-    float Tsave = T;
-    unsigned long long n_blend = 0, n_steps = 0, n_live = 0;
-    uint32_t endp = 0;
-    uint32_t stopl = range.y;
-#pragma unroll
-    for (int q = 0; q < kMaxWaveViews; ++q) {
-        if (q >= n_runs) break;
-        const bool in = (T > 0.0f) & (my_run == q);
-        float x0 = in ? px : 3e38f, x1 = in ? px : -3e38f, y0 = in ? py : 3e38f, y1 = in ? py : -3e38f;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) {
-            x0 = fminf(x0, __shfl_xor(x0, d, 64));
-            x1 = fmaxf(x1, __shfl_xor(x1, d, 64));
-            y0 = fminf(y0, __shfl_xor(y0, d, 64));
-            y1 = fmaxf(y1, __shfl_xor(y1, d, 64));
-        }
-        if (lane == 0) s_box[wv][q] = make_float4(x0, x1, y0, y1);
-    }
-    {
-        const bool wave_done = __ballot(T > 0.0f) == 0;  // (the vote over all lanes, then lane 0 writes)
-        if (lane == 0) s_done[wv] = wave_done ? 1u : 0u;
-    }
-    if (threadIdx.x < 2) {
-        // the padding entry: zero opacity, never passes the cutoff
-        s_a[threadIdx.x][kPad] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_c[threadIdx.x][kPad] = make_float4(0.f, 0.f, 0.f, -__builtin_inff());
-        s_h[threadIdx.x][kPad] = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int v = 0; v < kGroupViews; ++v) s_mu[threadIdx.x][v][kPad] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-
-    // issue the loads of the batch at `base` (Gaussian indices idx) into LDS
-    // buffer b: this wavefront's parts k * nt + wv (at most 5, since a group
-    // of n items has at most 4 n views)
-    const int n_parts = 1 + nv;
-    auto issue = [&](int b, uint32_t idx) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int part = k * nt + wv;
-            if (part == 0) {
-                load_to_lds(&rec[idx].a, &s_a[b][0]);
-                load_to_lds(&rec[idx].c, &s_c[b][0]);
-            } else if (part < n_parts) {
-                load_to_lds(bp.mean2d + (int64_t)G.slot[part - 1] * bp.M + idx, &s_mu[b][part - 1][0]);
-            }
-        }
-    };
-    // Gaussian index of this lane's entry in the batch at `base` (entries
-    // past the list read Gaussian 0's data, which the cutoff marks unusable)
-    auto index_at = [&](uint32_t base) -> uint32_t {
-        const uint32_t e = base + (uint32_t)lane;
-        return e < range.y ? bp.vals[e] : 0u;
-    };
-    // after a batch landed in buffer b: cutoff exponent and culling extents of
-    // its entries (wavefront 0)
-    auto prepare = [&](int b, uint32_t base) {
-        if (wv != 0) return;
-        const float4 a = s_a[b][lane];
-        const float thr = base + (uint32_t)lane < range.y ? cutoff_exponent(a.w) : -__builtin_inff();
-        float hx = 0.0f, hy = 0.0f;
-        if (thr >= 0.0f) {
-            hy = sqrtf(thr / a.z) * 1.001f + 1e-3f;
-            hx = sqrtf(thr / a.x) * 1.001f + fabsf(a.y) * hy + 1e-3f;
-        }
-        s_c[b][lane].w = thr;
-        s_h[b][lane] = make_float2(hx, hy);
-    };
-    auto landed = [&]() {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's loads are in LDS
-        __syncthreads();
-    };
-
-    if (range.x < range.y) {
-        issue(0, index_at(range.x));
-        uint32_t nidx = range.x + kWave < range.y ? index_at(range.x + kWave) : 0u;
-        landed();
-        prepare(0, range.x);
-        __syncthreads();
-        int cur = 0;
-        for (uint32_t base = range.x; base < range.y; base += kWave) {
-            bool all_done = true;
-            for (int t = 0; t < nt; ++t) all_done = all_done && s_done[t] != 0u;
-            if (all_done) break;
-            const bool more = base + kWave < range.y;
-            if (more) {
-                issue(cur ^ 1, nidx);
-                if (base + 2 * kWave < range.y) nidx = index_at(base + 2 * kWave);
-            }
-            if (!s_done[wv]) {
-                // the staged entries that can reach an unfinished lane of this
-                // wavefront: the region E <= E_cut lies in |dy| <= hy,
-                // |dx| <= hx around the entry's mean (widened for rounding);
-                // outside it alpha < 0.9986 / 255 for every lane
-                const float thr = s_c[cur][lane].w;
-                const float2 h = s_h[cur][lane];
-                bool rel = false;
-                if (thr >= 0.0f) {
-#pragma unroll
-                    for (int q = 0; q < kMaxWaveViews; ++q) {
-                        if (q >= n_runs) break;
-                        const float4 bx = s_box[wv][q];
-                        const float4 m = s_mu[cur][gview[q]][lane];
-                        rel = rel | ((m.x + h.x >= bx.x) & (m.x - h.x <= bx.y) & (m.y + h.y >= bx.z) &
-                                     (m.y - h.y <= bx.w));
-                    }
-                }
-                const uint64_t rmask = __ballot(rel);
-                const int nb = __popcll(rmask);
-                if (rel) s_rel[wv][__popcll(rmask & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-                const int nb4 = (nb + 3) & ~3;
-                if (lane >= nb && lane < nb4) s_rel[wv][lane] = (uint8_t)kPad;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                for (int g0 = 0; g0 < nb4; g0 += 16) {
-                    const int g1 = min(g0 + 16, nb4);
-                    for (int g4 = g0; g4 < g1; g4 += 4) {
-                        float4 A[4];
-                        float2 MU[4];
-                        float CU[4], TH[4];
-                        int EI[4];
-#pragma unroll
-                        for (int gk = 0; gk < 4; ++gk) {
-                            const int ei = s_rel[wv][g4 + gk];
-                            EI[gk] = ei;
-                            A[gk] = s_a[cur][ei];
-                            const float4 cc = s_c[cur][ei];
-                            CU[gk] = u == 0 ? cc.x : (u == 1 ? cc.y : cc.z);
-                            TH[gk] = cc.w;
-                            const float4 mm = s_mu[cur][my_gv][ei];
-                            MU[gk] = make_float2(mm.x, mm.y);
-                        }
-                        StepEval st[4];
-                        float E[4];
-#pragma unroll
-                        for (int gk = 0; gk < 4; ++gk) E[gk] = step_exponent(A[gk], MU[gk], px, py, st[gk]);
-                        uint64_t within[4];
-#pragma unroll
-                        for (int gk = 0; gk < 4; ++gk) within[gk] = __ballot(E[gk] <= TH[gk]);
-                        const bool skip_group =
-                            ((within[0] | within[1] | within[2] | within[3]) & __ballot(T > 0.0f)) == 0;
-                        if (kCount) n_steps += lane == 0 ? (unsigned)min(4, nb - g4) : 0u;
-                        if (skip_group) continue;
-#pragma unroll
-                        for (int gk = 0; gk < 4; ++gk) {
-                            if ((within[gk] & __ballot(T > 0.0f)) == 0) continue;
-                            const float alpha = step_alpha_of(A[gk].w, E[gk], st[gk]);
-                            const float Tn = T * (1.0f - alpha);
-                            const bool pass = alpha >= kAlphaMin;
-                            const bool take = pass & (Tn >= kTStop);
-                            const bool stop = pass & !take & (T > 0.0f);
-                            if (kCount) {
-                                n_blend += take ? 1u : 0u;
-                                const bool live = __ballot(pass & (T > 0.0f)) != 0;
-                                n_live += (lane == 0 && live) ? 1u : 0u;
-                                stopl = stop ? base + (uint32_t)EI[gk] + 1u : stopl;
-                            }
-                            const float wgt = take ? CU[gk] * alpha : 0.0f;
-                            const float Ct = fmaf(wgt, T, C);
-                            C = stop ? C + T * bgu : Ct;
-                            if (kSave) {
-                                endp = take ? base + (uint32_t)EI[gk] + 1u : endp;
-                                Tsave = stop ? T : (take ? Tn : Tsave);
-                            }
-                            T = take ? Tn : (stop ? 0.0f : T);
-                        }
-                    }
-                    if (__ballot(T > 0.0f) == 0) break;
-                }
-                const bool wave_done = __ballot(T > 0.0f) == 0;
-                if (lane == 0 && wave_done) s_done[wv] = 1u;
-            }
-            if (more) {
-                landed();
-                prepare(cur ^ 1, base + kWave);
-            }
-            __syncthreads();
-            cur ^= 1;
-        }
-    }
-    if (!task_live) return;
-    const bool done = T == 0.0f;
-    const uint64_t newly = __ballot(active && done && !was_done);
-    const bool all_done = __ballot(!done) == 0;
-    if (all_done || bp.last) {
-        if (active) {
-            out[p] = C + T * bgu;
-            if (kSave) {
-                bp.save_T[p] = Tsave;
-                bp.save_end[p] = endp;
-            }
-        }
-    } else if (active) {
-        state[at] = make_float2(T, C);
-    }
-    if (lane == 0) {
-        if (all_done) bp.task_alive[ti] = 0;
-        const uint32_t nn = (uint32_t)__popcll(newly);
-        if (nn) {
-            atomicSub(&bp.tc_alive[list], nn);
-            atomicSub(bp.alive_total, nn);
-        }
-    }
-    if (kCount) {
-        add_work(bp.work, was_done ? 0ull : (unsigned long long)(stopl - range.x));
-        add_work(bp.work + 1, n_blend);
-        add_work(bp.work + 2, n_steps);
-        add_work(bp.work + 3, n_live);
-    }
-}
-
 // Row-major thread order (no remap): a 256-thread block per tile, each
 // thread takes subpixels r = tid, tid+256, ... of the tile's row-major list
 // and walks its own (tile, cluster) list from global memory.  State is kept
@@ -1016,22 +718,6 @@ hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_ta
         hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks);
     else
         hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks);
-    return hipGetLastError();
-}
-
-hipError_t launch_blend_group(const BlendParams &bp, const Task *tasks, const TaskGroup *groups, int n_groups,
-                              hipStream_t s)
-{
-    if (n_groups == 0) return hipSuccess;
-    const dim3 grid(xcd_grid(n_groups)), block(kGroupTasks * kWave);
-    if (bp.work && bp.save_T)
-        hipLaunchKernelGGL((blend_group_kernel<true, true>), grid, block, 0, s, bp, tasks, groups, n_groups);
-    else if (bp.work)
-        hipLaunchKernelGGL((blend_group_kernel<true, false>), grid, block, 0, s, bp, tasks, groups, n_groups);
-    else if (bp.save_T)
-        hipLaunchKernelGGL((blend_group_kernel<false, true>), grid, block, 0, s, bp, tasks, groups, n_groups);
-    else
-        hipLaunchKernelGGL((blend_group_kernel<false, false>), grid, block, 0, s, bp, tasks, groups, n_groups);
     return hipGetLastError();
 }
 

@@ -72,20 +72,6 @@ struct alignas(16) Task {
 };
 static_assert(sizeof(Task) == 32, "Task must be 32 bytes");
 
-// The blend work items of one (tile, cluster) list that run as one
-// workgroup sharing each fetched batch: up to kGroupTasks consecutive items
-// with up to kGroupViews distinct views between them.
-constexpr int kGroupTasks = 8;
-constexpr int kGroupViews = 8;
-struct alignas(16) TaskGroup {
-    uint32_t first;                // first item
-    uint16_t n_tasks;              // 1..kGroupTasks
-    uint16_t n_views;              // 1..kGroupViews
-    uint16_t slot[kGroupViews];    // compact mean slots of the views (0 beyond n_views)
-    uint32_t pad[2];
-};
-static_assert(sizeof(TaskGroup) == 32, "TaskGroup must be 32 bytes");
-
 // Per-render cluster/view tables (device copies live in the context).
 struct ViewTables {
     int n_clusters = 0;          // K'
@@ -103,8 +89,6 @@ struct ViewTables {
 struct TaskSet {
     Task *d_tasks = nullptr;
     int n = 0;
-    TaskGroup *d_groups = nullptr;        // the items grouped by (tile, cluster) list
-    int n_groups = 0;
     int32_t *d_view_cluster = nullptr;    // [N]
     uint32_t *d_tc_count = nullptr;       // [T << cluster_bits]
     int cluster_bits = 0;
@@ -316,8 +300,6 @@ struct BlendParams {
     uint32_t *save_end;           // per subpixel: 1 + position of its last blended pair (0: none)
 };
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
-                              hipStream_t s);
-hipError_t launch_blend_group(const BlendParams &bp, const Task *tasks, const TaskGroup *groups, int n_groups,
                               hipStream_t s);
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
 
