@@ -80,7 +80,7 @@ def kernel_source_hash():
 def measured_traffic(kernel, workload, tile):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None if there is none for this workload, tile shape and kernel source."""
-    path = os.path.join(ROOT, "profiles", "blend_outdoor_traffic.json")
+    path = os.path.join(ROOT, "profiles", "blend_remap_outdoor_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -562,9 +562,9 @@ def main():
     bl = max(blend_launches / args.steps, 1.0)
     blend_ms = stages["ms_blend"] / bl
     ops_per_launch = OPS_PER_EVAL * work["evals"] / bl
-    roofline = {"bound": "alu", "kernel": "blend_group_kernel<false, false>",
+    roofline = {"bound": "alu", "kernel": "blend_remap_kernel<false, false>",
                 "achieved": ops_per_launch / (blend_ms * 1e-3) / 1e12, "peak": PEAK_VALU_TOPS, "unit": "T lane-ops/s",
-                "traffic": measured_traffic("blend_group_kernel<false, false>", w.name,
+                "traffic": measured_traffic("blend_remap_kernel<false, false>", w.name,
                                             (params.tile_w, params.tile_h)),
                 "launch_ms": blend_ms, "launches_per_frame": bl, "ops_per_launch": ops_per_launch,
                 "ops_per_eval": OPS_PER_EVAL, "evals": work["evals"], "blended": work["blended"],
