@@ -341,6 +341,20 @@ lfr_status lfr_sort_pairs_u32(lfr_context *ctx, uint32_t *keys_device, uint32_t 
 lfr_status lfr_sort_pairs_u64(lfr_context *ctx, uint64_t *keys_device, uint32_t *values_device,
                               int64_t n, int32_t begin_bit, int32_t end_bit);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as lfr_sort_pairs_u32 (identical output), with uint32 keys only and
+ * n <= 4,194,304 (2^22; larger n returns LFR_ERR_CAPACITY and enqueues
+ * nothing).  Its ping-pong buffers and histograms live in a fixed 36 MiB
+ * device array that the library holds on each GPU it runs on until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocating
+ * call (the first call on a device looks the array's address up).  Every
+ * call on one GPU shares that array, from any context: calls that may
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialized by the caller. */
+lfr_status lfr_sort_pairs_u32_noalloc(lfr_context *ctx, uint32_t *keys_device, uint32_t *values_device,
+                                      int64_t n, int32_t begin_bit, int32_t end_bit);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <numeric>
 
 #include "lfr_internal.h"
@@ -1603,6 +1604,80 @@ lfr_status lfr_sort_pairs_u32(lfr_context *ctx, uint32_t *keys, uint32_t *vals, 
 lfr_status lfr_sort_pairs_u64(lfr_context *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t b0, int32_t b1)
 {
     return sort_pairs<uint64_t>(ctx, keys, vals, n, b0, b1);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free sort
+// ---------------------------------------------------------------------------
+namespace {
+
+// The largest n lfr_sort_pairs_u32_noalloc takes, and the fixed device
+// scratch it uses in place of the context workspace: the second key and
+// value buffers of the ping-pong, then the radix histograms, their offsets
+// and the scan's partial sums.
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 22;
+constexpr size_t kNoAllocPingBytes = (size_t)kNoAllocMaxPairs * sizeof(uint32_t);
+constexpr size_t kNoAllocTempBytes = size_t(4) << 20;
+constexpr size_t kNoAllocScratchBytes = 2 * kNoAllocPingBytes + kNoAllocTempBytes;
+
+// One copy per GPU, kept until the process ends (36 MiB).  In host code the
+// name is a host-side stand-in, not a device address: host code only uses
+// the per-device address that noalloc_scratch() resolves.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices];
+
+// The device address of `scratch` on the context's device (current after
+// begin()), looked up on the first call on that device.
+lfr_status noalloc_scratch(lfr_context *ctx, void **out)
+{
+    if (ctx->device < 0 || ctx->device >= kNoAllocMaxDevices)
+        return fail(ctx, LFR_ERR_UNSUPPORTED, "device %d is beyond the allocation-free scratch table", ctx->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+        void *p = nullptr;
+        HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ctx, LFR_ERR_HIP, "no device address for the allocation-free scratch");
+        g_scratch_ptr[ctx->device] = p;
+    }
+    *out = g_scratch_ptr[ctx->device];
+    return LFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lfr_status lfr_sort_pairs_u32_noalloc(lfr_context *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t b0,
+                                      int32_t b1)
+{
+    CHK(begin(ctx));
+    if (n < 0 || (n > 0 && (!keys || !vals)) || b0 < 0 || b1 > 32 || b0 > b1)
+        return fail(ctx, LFR_ERR_INVALID_ARG, "bad sort arguments");
+    if (n > kNoAllocMaxPairs)
+        return fail(ctx, LFR_ERR_CAPACITY, "n = %lld exceeds the allocation-free sort's limit of %lld pairs",
+                    (long long)n, (long long)kNoAllocMaxPairs);
+    if (n <= 1 || b0 == b1) return LFR_OK;
+    if (sort_temp_bytes(n) > kNoAllocTempBytes)
+        return fail(ctx, LFR_ERR_CAPACITY, "sort temporaries exceed the allocation-free scratch");
+    void *base = nullptr;
+    CHK(noalloc_scratch(ctx, &base));
+    uint32_t *k1 = (uint32_t *)base;
+    uint32_t *v1 = (uint32_t *)((char *)base + kNoAllocPingBytes);
+    void *tmp = (char *)base + 2 * kNoAllocPingBytes;
+    // every histogram, offset and partial the passes read is written by the
+    // same pass first, so nothing in the scratch needs clearing
+    bool alt = false;
+    HIPCHK(ctx, radix_sort_u32(keys, vals, k1, v1, n, b0, b1, tmp, &alt, ctx->stream));
+    if (alt) {
+        HIPCHK(ctx, hipMemcpyAsync(keys, k1, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(vals, v1, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return LFR_OK;
 }
 
 }  // extern "C"

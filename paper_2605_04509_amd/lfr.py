@@ -140,6 +140,7 @@ _SIGS = {
                                POINTER(lfr_tune_result), POINTER(lfr_tune_result)]),
     "lfr_sort_pairs_u32": (c_int32, [c_void_p, _P, _P, c_int64, c_int32, c_int32]),
     "lfr_sort_pairs_u64": (c_int32, [c_void_p, _P, _P, c_int64, c_int32, c_int32]),
+    "lfr_sort_pairs_u32_noalloc": (c_int32, [c_void_p, _P, _P, c_int64, c_int32, c_int32]),
 }
 
 _lib = None
@@ -554,4 +555,17 @@ def sort_pairs(ctx: Context, keys, values, begin_bit=0, end_bit=None):
         raise ValueError("keys must be 32- or 64-bit integers")
     end_bit = kb if end_bit is None else end_bit
     _check(fn(ctx.handle, _ptr(keys), _ptr(values), n, begin_bit, end_bit), ctx.handle)
+    return keys, values
+
+
+def sort_pairs_noalloc(ctx: Context, keys, values, begin_bit=0, end_bit=32):
+    """lfr_sort_pairs_u32_noalloc: the 32-bit-key sort without any device
+    allocation (fixed per-GPU scratch, n <= 2^22)."""
+    torch = _torch()
+    if keys.dtype not in (torch.int32, torch.uint32) or values.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("keys and values must be 32-bit integers")
+    if values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    _check(library().lfr_sort_pairs_u32_noalloc(ctx.handle, _ptr(keys), _ptr(values), keys.numel(), begin_bit,
+                                                end_bit), ctx.handle)
     return keys, values
