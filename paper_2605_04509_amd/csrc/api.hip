@@ -23,7 +23,7 @@ constexpr int64_t kFirstChunkDiv = 64;
 namespace {
 
 enum Slot {
-    kRec, kItems, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
+    kRec, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
     kAliveSat, kItemBox, kNumSlots
@@ -51,7 +51,7 @@ struct SavedForward {
     float bg[3] = {0.f, 0.f, 0.f};
     int n_clusters = 0, n_views = 0, cbits = 0;
     const DevCamera *cams = nullptr;
-    const int32_t *cluster_cam = nullptr, *view_cam = nullptr, *view_slot = nullptr;
+    const int32_t *cluster_cam = nullptr, *view_cam = nullptr, *view_slot = nullptr, *cv_off = nullptr;
     const GaussRec *rec = nullptr;
     const float2 *mean2d = nullptr;
     const uint2 *ranges = nullptr;
@@ -391,7 +391,6 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
 struct Projected {
     int64_t Mp = 0;             // stride of the depth-sorted per-cluster segments
     GaussRec *rec = nullptr;
-    ItemRec *items = nullptr;
     ushort4 *ibox = nullptr;
     float2 *mean2d = nullptr;
     const uint32_t *dks = nullptr;
@@ -416,7 +415,7 @@ Grid make_grid(int W, int H, int tw, int th)
 Grid grid_of(const lfr_display *d) { return make_grid(d->W, d->H, d->tw, d->th); }
 
 lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *scene, const DevTables &dt,
-                            const ViewTables &vt, Projected *out)
+                            const ViewTables &vt, bool planes, Projected *out)
 {
     const Grid *d = &d_;
     hipStream_t s = ctx->stream;
@@ -440,15 +439,14 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     uint32_t *dval1;
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
-    CHK(ws_get_t(ctx, kItems, MK, &po.items));
     CHK(ws_get_t(ctx, kItemBox, MK, &po.ibox));
     CHK(ws_get_t(ctx, kDKey0, MKp, &po.dkey));
     CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
     CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
     CHK(ws_get_t(ctx, kDVal1, MKp, &dval1));
-    // (+1: the blend fetches each mean with a 16-byte load, the last one's
-    // second half past the last plane)
-    CHK(ws_get_t(ctx, kMean2D, M * NV + 1, &po.mean2d));
+    // (the per-view mean planes only when something reads them)
+    po.mean2d = nullptr;
+    if (planes) CHK(ws_get_t(ctx, kMean2D, std::max<int64_t>(M * NV, 1), &po.mean2d));
     CHK(ws_get(ctx, kSortTemp, sort_temp_bytes(MKp), &sort_temp));
     const size_t e0 = tm.mark(s);
     const TileGrid tg{d->W, d->H, d->tw_shift, d->th_shift, dt.cv_off, dt.cv_list, dt.cv_cam};
@@ -459,7 +457,6 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     HIPCHK(ctx, radix_sort_u32(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, nullptr, nullptr, Mp));
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
-    out->items = po.items;
     out->ibox = po.ibox;
     out->mean2d = po.mean2d;
     out->dks = alt ? dkey1 : po.dkey;
@@ -471,7 +468,7 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
 }
 
 BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, int64_t M, int64_t Mp, int cbits,
-                     const uint32_t *alive, const ItemRec *items, const ushort4 *ibox, const float2 *mean2d)
+                     const uint32_t *alive, const GaussRec *items, const ushort4 *ibox)
 {
     const Grid *d = &d_;
     BinParams bp;
@@ -491,7 +488,6 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive_words = (d->TX + 31) / 32;
     bp.items = items;
     bp.ibox = ibox;
-    bp.mean2d = mean2d;
     bp.alive_total = nullptr;
     bp.alive_sat = nullptr;
     return bp;
@@ -843,6 +839,10 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
     Timer &tm = ctx->timer;
     const ViewTables vt1 = build_tables(d, S, cull);
     const ViewTables vt = merge_tables(vt1, F, d->N);
+    // the records index a cluster's means by slot - cv_off[k]: view slots are
+    // numbered in view order, cluster by cluster
+    for (size_t e = 0; e < vt.cv_list.size(); ++e)
+        if (vt.cv_list[e] != (int32_t)e) return fail(ctx, LFR_ERR_UNSUPPORTED, "view slots out of cluster order");
     TaskSet *ts = nullptr;
     CHK(get_group_layout(ctx, d, S, cull, vt1, F, &ts));
     tm.reset(!planned && (opts->flags & LFR_TIMING) != 0);
@@ -853,7 +853,11 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
     else
         CHK(upload_tables(ctx, d, cams, vt, &dt, outs, F > 1 ? F : 0));
     Projected pr;
-    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, &pr));
+    // the mean planes are read by the row-major blend and for clusters whose
+    // means do not fit in the record
+    bool planes = !remap;
+    for (int k = 0; k < vt.n_clusters; ++k) planes = planes || vt.cv_off[k + 1] - vt.cv_off[k] > kItemViews;
+    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, planes, &pr));
 
     // traversal state: unsaturated subpixels per (tile, cluster) list and in
     // total, the lists' alive bits, per-subpixel (T, C), per-item flags
@@ -894,6 +898,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
     bp.view_cluster = dt.view_cluster;
     bp.rec = pr.rec;
     bp.mean2d = pr.mean2d;
+    bp.cv_off = dt.cv_off;
     for (int k = 0; k < 3; ++k) bp.bg[k] = opts->background[k];
     bp.out = outs[0];
     bp.out_frames = F > 1 ? dt.out_frames : nullptr;
@@ -913,8 +918,9 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
         CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
         CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
     }
-    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox, pr.mean2d);
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.rec, pr.ibox);
     if (planned) bin.alive_total = &d_tot->alive;
+
 
     // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x.
     // The backward needs each subpixel's whole list in one chunk: a render
@@ -1015,6 +1021,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
         sv.view_slot = dt.view_slot;
         sv.rec = pr.rec;
         sv.mean2d = pr.mean2d;
+        sv.cv_off = dt.cv_off;
         sv.ranges = saved_chunk.ranges;
         sv.vals = saved_chunk.vals;
         sv.tasks = ts->d_tasks;
@@ -1380,6 +1387,7 @@ lfr_status lfr_render_backward(lfr_context *ctx, uint64_t saved_forward, const l
     bp.vals = sv.vals;
     bp.rec = sv.rec;
     bp.mean2d = sv.mean2d;
+    bp.cv_off = sv.cv_off;
     for (int k = 0; k < 3; ++k) bp.bg[k] = sv.bg[k];
     bp.grad_out = grad_out_device;
     bp.save_T = sv.save_T;
@@ -1447,14 +1455,14 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         DevTables dt;
         CHK(upload_tables(ctx, d, &host_cams, vt, &dt));
         Projected pr;
-        CHK(project_and_sort(ctx, fg, scene, dt, vt, &pr));
+        CHK(project_and_sort(ctx, fg, scene, dt, vt, true, &pr));
         // one chunk with every tile of every view alive
         uint32_t *alive_bits;
         Totals *d_tot;
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
-        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.items, pr.ibox, pr.mean2d);
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.rec, pr.ibox);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;

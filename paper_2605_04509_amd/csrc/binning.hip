@@ -18,11 +18,10 @@
 
 namespace lfr {
 
-// Units of an item: (tile row, 32-tile word) cells of its bounding box.
-__device__ inline int item_units(const ItemRec &r)
+// Units of an item: (tile row, 32-tile word) cells of its union tile box b.
+__device__ inline int item_units(ushort4 b)
 {
-    if (r.nv == 0) return 0;
-    return ((int)r.bbox.w - (int)r.bbox.z + 1) * (((int)r.bbox.y >> 5) - ((int)r.bbox.x >> 5) + 1);
+    return ((int)b.w - (int)b.z + 1) * (((int)b.y >> 5) - ((int)b.x >> 5) + 1);
 }
 
 // Whether any (tile, cluster k) list inside the tile rectangle b (inclusive
@@ -36,51 +35,82 @@ __device__ inline bool rect_alive(const BinParams &bp, int k, ushort4 b)
     return S[y1 * pitch + x1] - S[y0 * pitch + x1] - S[y1 * pitch + x0] + S[y0 * pitch + x0] != 0u;
 }
 
-// Pixel columns [c0, c1] whose centres in pixel rows [y0, y1] can lie in the
-// cutoff ellipse E <= E_c of record r at mean m, E = a (dx + beta dy)^2 + g dy^2.
-// For dy in an interval inside |dy| <= sqrt(E_c / g), the ellipse's right
-// edge -beta dy + sqrt((E_c - g dy^2) / a) is concave and peaks at
-// dy* = -beta sqrt(E_c / S) / g, S = 1/a + beta^2/g (where the edge reaches
-// the full half width sqrt(E_c S)); the left edge is its mirror image.  So
-// the extremes over the row band are at dy* clamped into it.  E_c is the
-// record's cutoff widened by 0.1% and 1e-3, and the span by 1e-4 relative
-// and 0.02 px: margins far above the float32 error of this evaluation and of
-// the blend's.  Returns false when no centre of the band can be inside.
-__device__ inline bool row_span(const ItemRec &r, float2 m, int y0, int y1, int W, int &c0, int &c1)
+// The x-range [xl, xr] (relative to the mean, padded) of the cutoff ellipse
+// E <= E_c of record r, E = a (dx + beta dy)^2 + g dy^2, over the rows dy in
+// [dlo, dhi]; false when no such row meets it.  For dy in an interval inside
+// |dy| <= sqrt(E_c / g), the ellipse's right edge -beta dy + sqrt((E_c - g
+// dy^2) / a) is concave and peaks at dy* = -beta sqrt(E_c / S) / g, S = 1/a
+// + beta^2/g (where the edge reaches the full half width sqrt(E_c S)); the
+// left edge is its mirror image.  So the extremes over the band are at dy*
+// clamped into it.  E_c is the record's cutoff widened by 0.1% and 1e-3, and
+// the range by 1e-4 relative and 0.02 px: margins far above the float32
+// error of this evaluation and of the blend's.
+__device__ inline bool ellipse_xrange(const GaussRec &r, float dlo, float dhi, float &xl, float &xr)
 {
-    const float Ec = r.ecut * 1.001f + 1e-3f;
-    const float hy = sqrtf(Ec / r.g);
-    const float lo = fmaxf((float)y0 + 0.5f - m.y, -hy), hi = fminf((float)y1 + 0.5f - m.y, hy);
+    const float ra = r.a.x, rbeta = r.a.y, rg = r.a.z;
+    const float Ec = r.c.w * 1.001f + 1e-3f;
+    const float hy = sqrtf(Ec / rg);
+    const float lo = fmaxf(dlo, -hy), hi = fminf(dhi, hy);
     if (!(lo <= hi)) return false;
-    const float S = 1.0f / r.a + r.beta * r.beta / r.g;
-    const float ds = -r.beta * sqrtf(Ec / S) / r.g;
+    const float S = 1.0f / ra + rbeta * rbeta / rg;
+    const float ds = -rbeta * sqrtf(Ec / S) / rg;
     const float t1 = fminf(fmaxf(ds, lo), hi), t2 = fminf(fmaxf(ds, -hi), -lo);
-    const float xr = -r.beta * t1 + sqrtf(fmaxf(Ec - r.g * t1 * t1, 0.0f) / r.a);
-    const float xl = r.beta * t2 - sqrtf(fmaxf(Ec - r.g * t2 * t2, 0.0f) / r.a);
+    xr = -rbeta * t1 + sqrtf(fmaxf(Ec - rg * t1 * t1, 0.0f) / ra);
+    xl = rbeta * t2 - sqrtf(fmaxf(Ec - rg * t2 * t2, 0.0f) / ra);
     const float pad = 1e-4f * fmaxf(fabsf(xr), fabsf(xl)) + 0.02f;
-    // pixel x is covered when its centre x + 0.5 lies in [m.x + xl, m.x + xr]
-    const float f0 = fmaxf(ceilf(m.x + xl - pad - 0.5f), 0.0f);
-    const float f1 = fminf(floorf(m.x + xr + pad - 0.5f), (float)(W - 1));
+    xl -= pad;
+    xr += pad;
+    return true;
+}
+
+// Pixel columns [c0, c1] of the panel whose centres x + 0.5 lie in [xa, xb].
+__device__ inline bool centre_cols(float xa, float xb, int W, int &c0, int &c1)
+{
+    const float f0 = fmaxf(ceilf(xa - 0.5f), 0.0f);
+    const float f1 = fminf(floorf(xb - 0.5f), (float)(W - 1));
     if (!(f0 <= f1)) return false;
     c0 = (int)f0;
     c1 = (int)f1;
     return true;
 }
 
-// Tiles of the item (Gaussian i, cluster k) in unit u: the OR over the
-// cluster's views of the tiles in the unit's row and word that the view's
-// ellipse span covers, restricted to alive lists.  The record holds the
-// means of up to kItemViews views whose boxes meet the panel; when the
-// cluster has more such views (flags bit 0), every view's mean is read from
-// the mean planes instead (an invalid view's far stand-in mean covers
-// nothing).  Also returns the unit's row and word.
-__device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, const ItemRec &r, int u, int &ty, int &w)
+// Pixel columns [c0, c1] whose centres in pixel rows [y0, y1] can lie in the
+// cutoff ellipse of record r at mean m.
+__device__ inline bool row_span(const GaussRec &r, float2 m, int y0, int y1, int W, int &c0, int &c1)
 {
-    const int w0 = (int)r.bbox.x >> 5;
-    const int nw = ((int)r.bbox.y >> 5) - w0 + 1;
+    float xl, xr;
+    if (!ellipse_xrange(r, (float)y0 + 0.5f - m.y, (float)y1 + 0.5f - m.y, xl, xr)) return false;
+    return centre_cols(m.x + xl, m.x + xr, W, c0, c1);
+}
+
+// The same for the union over several views whose means lie in the box
+// [lo, hi]: each view's span lies in [m.x + xl, m.x + xr] with xl, xr taken
+// over its own rows dy in [y0 + 0.5 - m.y, y1 + 0.5 - m.y], a sub-band of
+// [y0 + 0.5 - hi.y, y1 + 0.5 - lo.y]; so [lo.x + xl, hi.x + xr] over that
+// band holds all of them.
+__device__ inline bool hull_span(const GaussRec &r, float2 lo, float2 hi, int y0, int y1, int W, int &c0, int &c1)
+{
+    float xl, xr;
+    if (!ellipse_xrange(r, (float)y0 + 0.5f - hi.y, (float)y1 + 0.5f - lo.y, xl, xr)) return false;
+    return centre_cols(lo.x + xl, hi.x + xr, W, c0, c1);
+}
+
+// Tiles of the item (Gaussian i, cluster k, union tile box b) in unit u: the
+// OR over the cluster's views of the tiles in the unit's row and word that
+// the view's ellipse span covers, restricted to alive lists.  The record
+// holds the means of a cluster with up to kItemViews views (an invalid
+// view's far stand-in mean covers nothing); for a larger cluster it holds
+// the bounding box of the means of the views whose tile box is non-empty,
+// and the row's span is that of the whole box (hull_span).  Also returns
+// the unit's row and word.
+__device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, const GaussRec &r, ushort4 b, int u,
+                                     int &ty, int &w)
+{
+    const int w0 = (int)b.x >> 5;
+    const int nw = ((int)b.y >> 5) - w0 + 1;
     // (most items span one or two words: no integer division for those)
     const int uq = nw == 1 ? u : (nw == 2 ? u >> 1 : u / nw);
-    ty = (int)r.bbox.z + uq;
+    ty = (int)b.z + uq;
     w = w0 + (u - uq * nw);
     const int xb = w << 5;
     auto bits = [&](int lo, int hi) -> uint32_t {  // tiles [lo, hi] within the word
@@ -92,20 +122,18 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, con
         return mh & ml;
     };
     // the unit's word clipped to the item's box
-    const uint32_t box = bits((int)r.bbox.x, (int)r.bbox.y);
+    const uint32_t box = bits((int)b.x, (int)b.y);
     uint32_t m = 0;
     const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
-    if (r.flags) {
-        for (int v = bp.cv_off[k]; v < bp.cv_off[k + 1]; ++v) {
-            const float2 mv = bp.mean2d[(int64_t)bp.cv_list[v] * bp.M + i];
-            int c0, c1;
-            if (row_span(r, mv, y0, y1, bp.W, c0, c1))
-                m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
-        }
+    const int v0 = bp.cv_off[k], nvk = bp.cv_off[k + 1] - v0;
+    if (nvk > kItemViews) {
+        int c0, c1;
+        if (hull_span(r, r.m[0], r.m[1], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
     } else {
-        for (int v = 0; v < (int)r.nv; ++v) {
+#pragma unroll
+        for (int v = 0; v < kItemViews; ++v) {
             int c0, c1;
-            if (row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
+            if (v < nvk && row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
         }
     }
     const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;
@@ -115,15 +143,26 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, con
 // The record of lane `owner`, handed over through lane exchanges (the lanes
 // that work on an item's units read it from the lane that loaded it, not
 // from memory).
-__device__ __forceinline__ ItemRec shfl_item(const ItemRec &own, int owner)
+__device__ __forceinline__ GaussRec shfl_item(const GaussRec &own, int owner)
 {
     uint32_t w[16];
-    __builtin_memcpy(w, &own, sizeof(ItemRec));
+    __builtin_memcpy(w, &own, sizeof(GaussRec));
 #pragma unroll
     for (int k = 0; k < 16; ++k) w[k] = (uint32_t)__shfl((int)w[k], owner, 64);
-    ItemRec r;
-    __builtin_memcpy(&r, w, sizeof(ItemRec));
+    GaussRec r;
+    __builtin_memcpy(&r, w, sizeof(GaussRec));
     return r;
+}
+
+__device__ __forceinline__ ushort4 shfl_box(ushort4 own, int owner)
+{
+    uint32_t w[2];
+    __builtin_memcpy(w, &own, sizeof(ushort4));
+    w[0] = (uint32_t)__shfl((int)w[0], owner, 64);
+    w[1] = (uint32_t)__shfl((int)w[1], owner, 64);
+    ushort4 b;
+    __builtin_memcpy(&b, w, sizeof(ushort4));
+    return b;
 }
 
 // Position of the k-th set bit of m (k < popcount(m)).
@@ -192,10 +231,11 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         if (!kEmit && in) counts[o] = 0u;
         return;
     }
-    const ItemRec *items_k = bp.items + (int64_t)k * bp.M;
+    const GaussRec *items_k = bp.items + (int64_t)k * bp.M;
     uint32_t i = 0;
     int U = 0;
-    ItemRec own = {};  // this lane's item record (when it has units)
+    GaussRec own = {};  // this lane's item record and union tile box (when it has units)
+    ushort4 obox = make_ushort4(0, 0, 0, 0);
     // a cluster without any list that still has unsaturated subpixels emits
     // nothing (the summed-area table's total)
     const bool cluster_alive =
@@ -209,9 +249,10 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
             // items whose tiles are all saturated emit nothing: the counting
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
-            if (kEmit || !bp.alive_sat || rect_alive(bp, k, bp.ibox[(int64_t)k * bp.M + i])) {
+            obox = bp.ibox[(int64_t)k * bp.M + i];
+            if (kEmit || !bp.alive_sat || rect_alive(bp, k, obox)) {
                 own = items_k[i];
-                U = item_units(own);
+                U = item_units(obox);
             }
         }
     }
@@ -229,8 +270,9 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         const uint32_t uloc = (has ? u : utot - 1) - (uint32_t)__shfl((int)ubase, owner, 64);
         int ty = 0, w = 0;
         uint32_t m = 0;
-        const ItemRec rown = shfl_item(own, owner);
-        if (has) m = unit_mask(bp, k, iown, rown, (int)uloc, ty, w);
+        const GaussRec rown = shfl_item(own, owner);
+        const ushort4 bown = shfl_box(obox, owner);
+        if (has) m = unit_mask(bp, k, iown, rown, bown, (int)uloc, ty, w);
         const uint32_t c = (uint32_t)__popc(m);
         if (!kEmit) {
             if (c) atomicAdd(&s_cnt[wave][owner], c);

@@ -45,15 +45,6 @@ __device__ __forceinline__ float step_eval(const float4 a, const float2 m, float
     return step_alpha_of(a.w, step_exponent(a, m, px, py, s), s);
 }
 
-// A bound on E beyond which alpha = o 2^-E is certainly below the 1/255
-// cutoff: log2(255 o) + 0.01 (there alpha <= 2^-0.01 / 255 = 0.993 / 255; the
-// margin dwarfs the float32 error of exp2, of log2 and of the product).  -inf
-// for o = 0.  Used only to skip evaluations whose outcome is already known.
-__device__ __forceinline__ float cutoff_exponent(float o)
-{
-    return __builtin_amdgcn_logf(255.0f * o) + 0.01f;
-}
-
 __device__ __forceinline__ float step_alpha(const float4 a, const float2 m, float px, float py)
 {
     StepEval s;
@@ -187,6 +178,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
     int slots[kMaxWaveViews];
 #pragma unroll
     for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = tk.slot[q];
+    // a cluster of at most kItemViews views keeps its means in the record, so
+    // an entry's conic, colour and means come from one cache line; the runs'
+    // views are then record slots (view slots are numbered in view order)
+    const int cv0 = bp.cv_off[tk.cluster];
+    const bool inline_means = bp.cv_off[tk.cluster + 1] - cv0 <= kItemViews;
 
     // Registers holding the batch being fetched, and the Gaussian indices of
     // the batch after it.  fetch() only issues loads (the record and means of
@@ -208,12 +204,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
         for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = make_float2(0.f, 0.f);
         if (e < range.y) {
             const uint32_t i = nidx;
-            const GaussRec g = rec[i];
-            ga = g.a;
-            gc = g.c;
+            ga = rec[i].a;
+            gc = rec[i].c;  // .w: the cutoff exponent
 #pragma unroll
             for (int q = 0; q < kMaxWaveViews; ++q)
-                if (q < n_runs) gm[q] = bp.mean2d[(int64_t)slots[q] * bp.M + i];
+                if (q < n_runs)
+                    gm[q] = inline_means ? rec[i].m[slots[q] - cv0] : bp.mean2d[(int64_t)slots[q] * bp.M + i];
         }
         load_index(base + kWave);
     };
@@ -223,7 +219,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
     // and 1e-3 px for rounding; outside it alpha < 0.9986 / 255 for every lane,
     // so dropping the Gaussian changes nothing.
     auto relevant = [&](uint32_t base) -> bool {
-        gc.w = cutoff_exponent(ga.w);
 #pragma unroll
         for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = sanitize_mean(gm[q]);
         if (base + (uint32_t)lane >= range.y) return false;
@@ -402,8 +397,8 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
         uint32_t endp = 0;
         for (uint32_t e = range.x; e < range.y; ++e) {
             const uint32_t i = bp.vals[e];
-            const GaussRec g = rec[i];
-            const float alpha = step_alpha(g.a, sanitize_mean(mu[i]), px, py);
+            const float4 ga = rec[i].a;
+            const float alpha = step_alpha(ga, sanitize_mean(mu[i]), px, py);
             if (kCount) ++n_eval;
             if (alpha < kAlphaMin) continue;
             const float Tn = T * (1.0f - alpha);
@@ -411,7 +406,8 @@ __global__ void __launch_bounds__(256) blend_rowmajor_kernel(BlendParams bp)
                 done = true;
                 break;
             }
-            const float col = u == 0 ? g.c.x : (u == 1 ? g.c.y : g.c.z);
+            const float4 gc = rec[i].c;
+            const float col = u == 0 ? gc.x : (u == 1 ? gc.y : gc.z);
             C = fmaf(col * alpha, T, C);
             T = Tn;
             endp = e + 1;
@@ -462,9 +458,8 @@ __global__ void __launch_bounds__(1024) blend_fullframe_kernel(FullFrameParams f
         __syncthreads();
         if ((int)threadIdx.x < nb) {
             const uint32_t i = fp.vals[base + threadIdx.x];
-            const GaussRec g = rec[i];
-            s_a[threadIdx.x] = g.a;
-            s_c[threadIdx.x] = g.c;
+            s_a[threadIdx.x] = rec[i].a;
+            s_c[threadIdx.x] = rec[i].c;
             s_mu[threadIdx.x] = sanitize_mean(mu[i]);
         }
         __syncthreads();
@@ -629,6 +624,8 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
 #pragma unroll
     for (int q = 0; q < kMaxWaveViews; ++q) slots[q] = tk.slot[q];
     const GaussRec *rec = bp.rec + (int64_t)tk.cluster * bp.M;
+    const int cv0 = bp.cv_off[tk.cluster];
+    const bool inline_means = bp.cv_off[tk.cluster + 1] - cv0 <= kItemViews;
     float *drec = reinterpret_cast<float *>(bp.d_rec + (int64_t)tk.cluster * bp.M);
     float *dmean = reinterpret_cast<float *>(bp.d_mean2d);
 
@@ -637,14 +634,14 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
         const int nb = (int)(top - b0);
         if (lane < nb) {
             const uint32_t i = bp.vals[b0 + lane];
-            GaussRec g = rec[i];
-            g.c.w = cutoff_exponent(g.a.w);
-            s_a[lane] = g.a;
-            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = g.c;
+            s_a[lane] = rec[i].a;
+            *reinterpret_cast<float4 *>(&s_c[lane * 4]) = rec[i].c;  // .w: the cutoff exponent
             s_i[lane] = i;
 #pragma unroll
             for (int q = 0; q < kMaxWaveViews; ++q)
-                if (q < n_runs) s_mu[q][lane] = sanitize_mean(bp.mean2d[(int64_t)slots[q] * bp.M + i]);
+                if (q < n_runs)
+                    s_mu[q][lane] = sanitize_mean(inline_means ? rec[i].m[slots[q] - cv0]
+                                                               : bp.mean2d[(int64_t)slots[q] * bp.M + i]);
         }
         __syncthreads();
         for (int g = nb - 1; g >= 0; --g) {

@@ -40,12 +40,22 @@ struct DevCamera {
     double campos[3];
 };
 
-// Per-(cluster, Gaussian) blend record: a = (A', beta, G', opacity),
-// c = (r, g, b, unused).
-struct GaussRec {
+// Per (cluster, Gaussian) record, written by the projection and read by
+// key generation and the blend: a = (A', beta, G', opacity), c = (r, g, b,
+// cutoff exponent log2(255 o) + 0.01, beyond which alpha < 1/255), and m:
+// for a cluster of at most kItemViews views the 2D mean in each of its views
+// in view order (kFarMean where the mean is invalid and beyond the cluster's
+// views), so that a blend lane's conic, colour and mean come from one cache
+// line; for a larger cluster (whose blend reads the mean planes) m[0], m[1]
+// are the smallest and largest x and y of the means of the views whose tile
+// box is non-empty, for key generation.
+constexpr int kItemViews = 4;
+struct alignas(64) GaussRec {
     float4 a;
     float4 c;
+    float2 m[kItemViews];
 };
+static_assert(sizeof(GaussRec) == 64, "GaussRec must be 64 bytes");
 
 // Per-(cluster, Gaussian) gradient record of the reverse blend, the same
 // layout as GaussRec: a = d(A', beta, G', opacity), c = d(r, g, b), unused.
@@ -169,25 +179,6 @@ hipError_t launch_task_emit(const uint16_t *V, const uint32_t *psi, const int32_
                             const int32_t *view_slot, int W, int H, int tw, int th, const uint32_t *offsets,
                             Task *tasks, hipStream_t s);
 
-// Per (cluster, Gaussian) binning record, written by the projection: the
-// union bounding box of the Gaussian's tile boxes over the cluster's views
-// (tile units, inclusive), the conic and cutoff exponent the blend uses, and
-// the 2D mean in each view whose box is non-empty (up to kItemViews).  Binning
-// covers, per tile row and view, the x-range of the cutoff ellipse over that
-// row; with more non-empty views than fit, `flags` bit 0 is set and binning
-// reads every view's mean from the mean planes.  64 B aligned.
-constexpr int kItemViews = 4;
-struct alignas(64) ItemRec {
-    uint16_t nv;
-    uint16_t flags;
-    float ecut;                // log2(255 o) + 0.01: alpha < 1/255 beyond it
-    ushort4 bbox;              // x0, x1, y0, y1
-    float a, beta, g;          // conic: E = a (dx + beta dy)^2 + g dy^2
-    float pad;
-    float2 m[kItemViews];      // mean in each view with a non-empty box
-};
-static_assert(sizeof(ItemRec) == 64, "ItemRec must be 64 bytes");
-
 struct SceneDev {
     int64_t M;
     int32_t deg;
@@ -195,11 +186,10 @@ struct SceneDev {
 };
 struct ProjectOut {
     GaussRec *rec;      // [K'][M]
-    ItemRec *items;     // [K'][M]  binning records
     ushort4 *ibox;      // [K'][M]  the records' union tile boxes (read alone to skip saturated items)
     uint32_t *dkey;     // [K'][Mp] float32 depth bits, 0xFFFFFFFF if invalid or padding
     uint32_t *dval;     // [K'][Mp] Gaussian index
-    float2 *mean2d;     // [N'][M]  (kFarMean, kFarMean) if the mean is invalid
+    float2 *mean2d;     // [N'][M]  (kFarMean, kFarMean) if the mean is invalid; null: not written
     int64_t Mp;         // M rounded up to the sort's segment granule
 };
 struct TileGrid {
@@ -247,9 +237,8 @@ struct BinParams {
     const int32_t *cv_list;   // compact view slots
     const uint32_t *alive;    // [K'][TY][alive_words] bit per (cluster, tile) list still needed
     int alive_words;          // 32-bit words per tile row
-    const ItemRec *items;     // [K'][M]
+    const GaussRec *items;    // [K'][M] the projection's records
     const ushort4 *ibox;      // [K'][M] union tile box of each record
-    const float2 *mean2d;     // [N'][M] per-view means (records with more views than they hold)
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
 };
@@ -283,14 +272,15 @@ struct BlendParams {
     const uint2 *ranges;
     const uint32_t *vals;         // sorted Gaussian indices
     const GaussRec *rec;          // [K'][M]
-    const float2 *mean2d;         // [N'][M]
+    const float2 *mean2d;         // [N'][M] (read for clusters of more than kItemViews views, and row-major)
+    const int32_t *cv_off;        // [K'+1] first view slot of each cluster (slots are in view order)
     float bg[3];
     float *out;                   // [H][W][3]
     float *const *out_frames;     // merged batch group: output of each frame (null: out)
     int64_t n_sub;                // 3 W H: per-frame stride of the traversal state
     unsigned long long *work;     // [2] evals, blended (counting variant only)
     // resumable traversal over depth chunks
-    float2 *state;                // per subpixel (T, C); T < 0 once saturated
+    float2 *state;                // per subpixel (T, C); saturated: T = 0 (remapped) or T < 0 (row-major)
     uint8_t *task_alive;          // per work item (remapped path)
     uint32_t *tc_alive;           // per (tile, cluster) list: unsaturated subpixels
     uint32_t *alive_total;        // unsaturated subpixels of the frame
@@ -301,6 +291,7 @@ struct BlendParams {
 };
 hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
                               hipStream_t s);
+
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
 
 // Reverse blend over the remapped work items of a saved single-chunk render.
@@ -315,6 +306,7 @@ struct BwdParams {
     const uint32_t *vals;
     const GaussRec *rec;          // [K'][M]
     const float2 *mean2d;         // [N'][M]
+    const int32_t *cv_off;        // [K'+1] first view slot of each cluster
     float bg[3];
     const float *grad_out;        // [H][W][3] dL/dI
     const float *save_T;

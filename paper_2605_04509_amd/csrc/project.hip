@@ -166,37 +166,25 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
 {
     FullProj f = {};
     const double *R = c.R;
-    // T1 = R Sigma (rows 0..2), Vc = T1 R^T (entries used below)
-    const double s00 = S.xx, s01 = S.xy, s02 = S.xz, s11 = S.yy, s12 = S.yz, s22 = S.zz;
-    const double a00 = (R[0] * s00 + R[1] * s01) + R[2] * s02;
-    const double a01 = (R[0] * s01 + R[1] * s11) + R[2] * s12;
-    const double a02 = (R[0] * s02 + R[1] * s12) + R[2] * s22;
-    const double a10 = (R[3] * s00 + R[4] * s01) + R[5] * s02;
-    const double a11 = (R[3] * s01 + R[4] * s11) + R[5] * s12;
-    const double a12 = (R[3] * s02 + R[4] * s12) + R[5] * s22;
-    const double a20 = (R[6] * s00 + R[7] * s01) + R[8] * s02;
-    const double a21 = (R[6] * s01 + R[7] * s11) + R[8] * s12;
-    const double a22 = (R[6] * s02 + R[7] * s12) + R[8] * s22;
-    const double v00 = (a00 * R[0] + a01 * R[1]) + a02 * R[2];
-    const double v01 = (a00 * R[3] + a01 * R[4]) + a02 * R[5];
-    const double v02 = (a00 * R[6] + a01 * R[7]) + a02 * R[8];
-    const double v11 = (a10 * R[3] + a11 * R[4]) + a12 * R[5];
-    const double v12 = (a10 * R[6] + a11 * R[7]) + a12 * R[8];
-    const double v20 = (a20 * R[0] + a21 * R[1]) + a22 * R[2];
-    const double v21 = (a20 * R[3] + a21 * R[4]) + a22 * R[5];
-    const double v22 = (a20 * R[6] + a21 * R[7]) + a22 * R[8];
+    // J (2 x 3, zero in (0,1) and (1,0)) at the clamped mean direction; with
+    // N = J R (2 x 3), Sigma2D = N Sigma N^T + 0.3 I: the quadratic forms of
+    // the symmetric Sigma in the rows n0, n1 of N
     const double cxl = m.ux < -c.limx ? -c.limx : (m.ux > c.limx ? c.limx : m.ux);
     const double cyl = m.uy < -c.limy ? -c.limy : (m.uy > c.limy ? c.limy : m.uy);
     const double j00 = c.fx * m.iz, j02 = -(c.fx * cxl) * m.iz;
     const double j11 = c.fy * m.iz, j12 = -(c.fy * cyl) * m.iz;
-    const double k00 = j00 * v00 + j02 * v20;
-    const double k01 = j00 * v01 + j02 * v21;
-    const double k02 = j00 * v02 + j02 * v22;
-    const double k11 = j11 * v11 + j12 * v21;
-    const double k12 = j11 * v12 + j12 * v22;
-    const double sa = (k00 * j00 + k02 * j02) + kDilation;
-    const double sb = k01 * j11 + k02 * j12;
-    const double sc = (k11 * j11 + k12 * j12) + kDilation;
+    const double n00 = j00 * R[0] + j02 * R[6], n01 = j00 * R[1] + j02 * R[7], n02 = j00 * R[2] + j02 * R[8];
+    const double n10 = j11 * R[3] + j12 * R[6], n11 = j11 * R[4] + j12 * R[7], n12 = j11 * R[5] + j12 * R[8];
+    // Sigma n0 and Sigma n1
+    const double u0 = (S.xx * n00 + S.xy * n01) + S.xz * n02;
+    const double u1 = (S.xy * n00 + S.yy * n01) + S.yz * n02;
+    const double u2 = (S.xz * n00 + S.yz * n01) + S.zz * n02;
+    const double w0 = (S.xx * n10 + S.xy * n11) + S.xz * n12;
+    const double w1 = (S.xy * n10 + S.yy * n11) + S.yz * n12;
+    const double w2 = (S.xz * n10 + S.yz * n11) + S.zz * n12;
+    const double sa = ((n00 * u0 + n01 * u1) + n02 * u2) + kDilation;
+    const double sb = (n00 * w0 + n01 * w1) + n02 * w2;
+    const double sc = ((n10 * w0 + n11 * w1) + n12 * w2) + kDilation;
     const double det = sa * sc - sb * sb;
     if (!(det > 0.0)) return f;
     const double rsc = recip(sc);
@@ -222,8 +210,10 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
     // the float32 evaluation error here and that of the blend.
     constexpr float kInvHalfLog2e = (float)(1.0 / kHalfLog2e);
     const float Ar = f.conic[0] * kInvHalfLog2e, br = f.conic[1], Gr = f.conic[2] * kInvHalfLog2e;
-    const float S00 = 1.0f / Ar + br * br / Gr, S11 = 1.0f / Gr;
-    f.ext = make_float2(sqrtf(tau_o * S00) * 1.0001f + 0.02f, sqrtf(tau_o * S11) * 1.0001f + 0.02f);
+    // (hardware reciprocals: their error of about one ulp is far inside the margins)
+    const float iG = __builtin_amdgcn_rcpf(Gr);
+    const float S00 = __builtin_amdgcn_rcpf(Ar) + (br * br) * iG, S11 = iG;
+    f.ext = make_float2(__builtin_sqrtf(tau_o * S00) * 1.0001f + 0.02f, __builtin_sqrtf(tau_o * S11) * 1.0001f + 0.02f);
     f.valid = isfinite(f.ext.x) && isfinite(f.ext.y);
     return f;
 }
@@ -252,20 +242,21 @@ __device__ inline void load_gaussian(const SceneDev &sc, int64_t i, GaussIn &g, 
     for (int k = 0; k < 3; ++k) {
         g.mu[k] = sc.means[3 * i + k];
         g.ls[k] = sc.log_scales[3 * i + k];
-        fin = fin && isfinite(g.mu[k]) && isfinite(g.ls[k]);
+        fin &= isfinite(g.mu[k]);
+        fin &= isfinite(g.ls[k]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         g.q[k] = sc.quats[4 * i + k];
-        fin = fin && isfinite(g.q[k]);
+        fin &= isfinite(g.q[k]);
     }
     g.o = sc.opac[i];
-    fin = fin && isfinite(g.o);
+    fin &= isfinite(g.o);
     const float *s = sc.sh + (int64_t)NB * 3 * i;
 #pragma unroll
     for (int k = 0; k < NB * 3; ++k) {
         if (from_scene) shc[k] = s[k];
-        fin = fin && isfinite(shc[k]);
+        fin &= isfinite(shc[k]);
     }
     g.finite = fin;
 }
@@ -367,57 +358,54 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, tau_o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
         out.dval[kidx] = (uint32_t)i;
-        // the cluster's views: mean planes, and the union of the tile boxes
-        // of this Gaussian's mean in each view with the cluster's extents
-        // (means placed by selects, not by a dynamic index, so that the
-        // record stays in registers)
+        // the cluster's views: mean planes, the record's means (the first
+        // kItemViews views, placed by selects rather than a dynamic index so
+        // that the record stays in registers), and the union of the tile
+        // boxes of this Gaussian's mean in each view with the cluster's extents
         float2 mv[kItemViews];
 #pragma unroll
-        for (int q = 0; q < kItemViews; ++q) mv[q] = make_float2(0.f, 0.f);
+        for (int q = 0; q < kItemViews; ++q) mv[q] = make_float2(kFarMean, kFarMean);
         int nv = 0;
         unsigned short x0 = 0xFFFF, x1 = 0, y0 = 0xFFFF, y1 = 0;
+        // a cluster of more views keeps the box of its binned views' means
+        float2 hlo = make_float2(kFarMean, kFarMean), hhi = make_float2(-kFarMean, -kFarMean);
         for (int v = tg.cv_off[k]; v < tg.cv_off[k + 1]; ++v) {
             const MeanProj mj = project_mean(cams[tg.cv_cam[v]], mx, my, mz, g.finite);
             const float2 m2 = mj.valid ? mj.m2d : make_float2(kFarMean, kFarMean);
-            out.mean2d[(int64_t)tg.cv_list[v] * M + i] = m2;
-            ushort4 b;
-            if (!f.valid || !mj.valid || !tile_box(m2, f.ext, tg, b)) continue;
+            if (out.mean2d) out.mean2d[(int64_t)tg.cv_list[v] * M + i] = m2;
+            const int l = v - tg.cv_off[k];
 #pragma unroll
             for (int q = 0; q < kItemViews; ++q)
-                if (q == nv) mv[q] = m2;
+                if (q == l) mv[q] = m2;
+            ushort4 b;
+            if (!f.valid || !mj.valid || !tile_box(m2, f.ext, tg, b)) continue;
             ++nv;
+            hlo = make_float2(fminf(hlo.x, m2.x), fminf(hlo.y, m2.y));
+            hhi = make_float2(fmaxf(hhi.x, m2.x), fmaxf(hhi.y, m2.y));
             x0 = min(x0, b.x);
             x1 = max(x1, b.y);
             y0 = min(y0, b.z);
             y1 = max(y1, b.w);
         }
         const bool binned = nv != 0;
-        ItemRec it;
-        it.nv = (uint16_t)(nv < kItemViews ? nv : kItemViews);
-        it.flags = nv > kItemViews ? 1 : 0;
-        it.ecut = ecut;
-        it.bbox = make_ushort4(x0, x1, y0, y1);
-        it.a = f.conic[0];
-        it.beta = f.conic[1];
-        it.g = f.conic[2];
-        it.pad = 0.0f;
-#pragma unroll
-        for (int q = 0; q < kItemViews; ++q) it.m[q] = mv[q];
         GaussRec r;
         r.a = make_float4(f.conic[0], f.conic[1], f.conic[2], g.o);
-        r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], 0.0f);
+        r.c = make_float4(f.colour[0], f.colour[1], f.colour[2], ecut);
+#pragma unroll
+        for (int q = 0; q < kItemViews; ++q) r.m[q] = mv[q];
+        if (tg.cv_off[k + 1] - tg.cv_off[k] > kItemViews) {
+            r.m[0] = hlo;
+            r.m[1] = hhi;
+        }
+        const ushort4 box = make_ushort4(x0, x1, y0, y1);
         if (full_wave) {
-            uint4 ip[4], rp[2];
-            __builtin_memcpy(ip, &it, sizeof(ItemRec));
+            uint4 rp[4];
             __builtin_memcpy(rp, &r, sizeof(GaussRec));
-            uint4 *buf = s_stage[threadIdx.x >> 6];
-            wave_store<4>(reinterpret_cast<uint4 *>(out.items + (idx - lane)), ip, lane, buf);
-            wave_store<2>(reinterpret_cast<uint4 *>(out.rec + (idx - lane)), rp, lane, buf);
-            out.ibox[idx] = it.bbox;
+            wave_store<4>(reinterpret_cast<uint4 *>(out.rec + (idx - lane)), rp, lane, s_stage[threadIdx.x >> 6]);
+            out.ibox[idx] = box;
         } else if (binned) {
-            out.items[idx] = it;
-            out.ibox[idx] = it.bbox;
             out.rec[idx] = r;
+            out.ibox[idx] = box;
         }
         out.dkey[kidx] = binned ? __float_as_uint(m.depth) : 0xFFFFFFFFu;
     }
