@@ -199,6 +199,17 @@ def display_bytes(p, clusters):
     return 2 * n_sub + 4 * n_sub + 32 * -(-n_sub // 64) + 4 * (n_tiles << cb)
 
 
+def finite_json(v):
+    """v with every non-finite float replaced by None (strict JSON has no inf or nan)."""
+    if isinstance(v, dict):
+        return {k: finite_json(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [finite_json(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
+
+
 def psnr_per_view(torch, img, ref, V, n_views):
     """PSNR (dB, peak 1, images clamped to [0, 1]) of the subpixels of each
     view of the display (V == j), like a per-view image metric: mean, min and
@@ -210,9 +221,12 @@ def psnr_per_view(torch, img, ref, V, n_views):
     used = cnt > 0
     mse = (sse[used] / cnt[used]).cpu().numpy()
     views = torch.nonzero(used).reshape(-1).cpu().numpy()
-    db = [float("inf") if m == 0.0 else 10.0 * math.log10(1.0 / m) for m in mse]
-    finite = [x for x in db if math.isfinite(x)] or [float("inf")]
-    return {"mean": sum(finite) / len(finite), "min": min(db), "max": max(db),
+    db = [None if m == 0.0 else 10.0 * math.log10(1.0 / m) for m in mse]
+    finite = [x for x in db if x is not None]
+    # (a view equal to the exact path, e.g. a cluster's representative, has no
+    # finite PSNR: reported as null and counted in `identical`)
+    return {"mean": sum(finite) / len(finite) if finite else None, "min": min(finite) if finite else None,
+            "max": max(finite) if finite else None, "identical": len(db) - len(finite),
             "views": {int(j): x for j, x in zip(views, db)}}
 
 
@@ -220,7 +234,7 @@ def psnr_db(torch, img, ref):
     """PSNR (dB, peak 1) of an interlaced image against a reference image, both
     clamped to [0, 1] as a display shows them, over every subpixel."""
     mse = float(((img.clamp(0.0, 1.0) - ref.clamp(0.0, 1.0)).double() ** 2).mean())
-    return float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+    return None if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
 
 
 def paper_shapes(args, torch, lfr, sync):
@@ -314,8 +328,8 @@ def batched(args, torch, lfr, sync):
             tried[str(S)] = {"ms": best_s["ms"], "tile": [best_s["tile_w"], best_s["tile_h"]],
                              "psnr_vs_exact_db": psnr_db(torch, img, exact)}
             del img
-            if tried[str(S)]["psnr_vs_exact_db"] >= BATCH_PSNR_FLOOR_DB and (choice is None or best_s["ms"] <
-                                                                            choice["ms"]):
+            q = tried[str(S)]["psnr_vs_exact_db"]   # None: identical to the exact path
+            if (q is None or q >= BATCH_PSNR_FLOOR_DB) and (choice is None or best_s["ms"] < choice["ms"]):
                 choice = best_s
         if choice is None:                  # no size keeps the floor: the smallest
             choice = min((r for r in res if r["cluster_size"] == BATCH_CLUSTER_SIZES[0]), key=lambda r: r["ms"])
@@ -693,7 +707,7 @@ def main():
 
     disp.close()
     ctx.close()
-    print(json.dumps(result), flush=True)
+    print(json.dumps(finite_json(result)), flush=True)
 
 
 if __name__ == "__main__":
