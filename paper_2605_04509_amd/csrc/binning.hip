@@ -242,10 +242,15 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
     if (in && cluster_alive) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
-        // (the emitting pass skips items the counting pass found empty
-        // without reading their records: most items of late chunks)
-        if (dkey_sorted[e] != 0xFFFFFFFFu && (!kEmit || counts[o] != 0u)) {
-            i = dval_sorted[e];
+        // key, index and (emitting pass) count are loaded together; the
+        // emitting pass skips items the counting pass found empty without
+        // reading their records: most items of late chunks
+        const uint32_t dk = dkey_sorted[e], dv = dval_sorted[e];
+        const uint32_t cnt = kEmit ? counts[o] : 1u;
+        // (the index is tested too, though never all ones, so that its load
+        // is issued with the key's instead of after the key is known)
+        if ((dk != 0xFFFFFFFFu) & (cnt != 0u) & (dv != 0xFFFFFFFFu)) {
+            i = dv;
             // items whose tiles are all saturated emit nothing: the counting
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
@@ -324,9 +329,12 @@ __global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict_
     const int64_t P = dP ? (int64_t)min(*dP, (uint64_t)P_cap) : P_cap;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    // the three loads are independent (clamped indices), so none waits for another
     const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = (uint32_t)p;
-    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (uint32_t)(p + 1);
+    const uint32_t kb = keys[p > 0 ? p - 1 : p];
+    const uint32_t ka = keys[p + 1 < P ? p + 1 : p];
+    if (p == 0 || kb != k) ranges[k].x = (uint32_t)p;
+    if (p == P - 1 || ka != k) ranges[k].y = (uint32_t)(p + 1);
 }
 
 // dst = *src (a device count recorded for the host to read later).
@@ -345,13 +353,19 @@ __global__ void __launch_bounds__(256) alive_bits_kernel(const uint32_t *__restr
     const int64_t rowid = wid / words;
     const int ty = (int)(rowid % TY);
     const int k = (int)(rowid / TY);
-    uint32_t m = 0;
+    // all 32 loads first (columns past the row read its last tile and are
+    // not counted)
+    uint32_t v[32];
+#pragma unroll
     for (int b = 0; b < 32; ++b) {
-        const int tx = (w << 5) + b;
-        if (tx >= TX) break;
+        const int tx = min((w << 5) + b, TX - 1);
         const uint32_t t = (uint32_t)(ty * TX + tx);
-        if (tc_alive[(t << cluster_bits) | (uint32_t)k] > 0) m |= 1u << b;
+        v[b] = tc_alive[(t << cluster_bits) | (uint32_t)k];
     }
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b)
+        if ((w << 5) + b < TX && v[b] > 0) m |= 1u << b;
     bits[wid] = m;
 }
 

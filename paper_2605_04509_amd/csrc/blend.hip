@@ -123,8 +123,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
 
     const int ti = xcd_task(blockIdx.x);
     if (ti >= n_tasks) return;
-    if (!bp.first && !bp.task_alive[ti]) return;
+    // the item and its alive flag are loaded together (the test reads both;
+    // an item always has at least one lane)
     const Task tk = tasks[ti];
+    if ((!bp.first && !bp.task_alive[ti]) || tk.count == 0) return;
     const int lane = threadIdx.x;
     const bool active = lane < (int)tk.count;
     const uint32_t at = tk.start + (active ? lane : (int)tk.count - 1);

@@ -276,7 +276,7 @@ __device__ inline bool tile_box(float2 m, float2 e, const TileGrid &tg, ushort4 
     return true;
 }
 
-constexpr int kProjBlock = 256;
+constexpr int kProjBlock = 64;
 
 // Store of the 64 lanes' records (Q pieces of 16 bytes each), consecutive in
 // memory from dst, as Q stores of 1 KB each, through the wavefront's 1 KB
@@ -321,9 +321,28 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
     {
         const int64_t nb = M - i0 < kProjBlock ? (M - i0 > 0 ? M - i0 : 0) : kProjBlock;
         const float *src = sc.sh + i0 * NS;
-        for (int e = threadIdx.x; e < (int)nb * NS; e += kProjBlock) {
-            const int r = e / NS;
-            s_sh[r * PITCH + (e - r * NS)] = src[e];
+        if (nb == kProjBlock) {
+            // a full block: 16 loads in flight before their LDS stores (a
+            // loop of load-then-store would wait for every load in turn)
+#pragma unroll
+            for (int c = 0; c < NS; c += 16) {
+                float v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (c + q < NS) v[q] = src[(c + q) * kProjBlock + threadIdx.x];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (c + q >= NS) break;
+                    const int e = (c + q) * kProjBlock + threadIdx.x;
+                    const int r = e / NS;
+                    s_sh[r * PITCH + (e - r * NS)] = v[q];
+                }
+            }
+        } else {
+            for (int e = threadIdx.x; e < (int)nb * NS; e += kProjBlock) {
+                const int r = e / NS;
+                s_sh[r * PITCH + (e - r * NS)] = src[e];
+            }
         }
     }
     __syncthreads();

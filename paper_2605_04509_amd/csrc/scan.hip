@@ -37,11 +37,19 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t 
 {
     __shared__ uint64_t ws[kScanBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // all loads first (index 0 stands in past the end and counts nothing):
+    // a load guarded by its own bounds test would wait for each in turn
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        const int64_t idx = base + it * kScanBlock + threadIdx.x;
+        v[it] = in[idx < n ? idx : 0];
+    }
     uint64_t s = 0;
 #pragma unroll
     for (int it = 0; it < kScanItems; ++it) {
         const int64_t idx = base + it * kScanBlock + threadIdx.x;
-        if (idx < n) s += in[idx];
+        s += idx < n ? v[it] : 0u;
     }
     uint64_t total;
     block_inclusive_scan(s, ws, &total);

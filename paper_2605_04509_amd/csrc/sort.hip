@@ -42,10 +42,20 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    // all of a thread's keys are loaded before the first is counted (a
+    // load guarded by its own bounds test would wait for each in turn)
+    // (indices past the count read element 0, which the grid's capacity
+    // always holds, and are not counted)
+    K k[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t idx = base + it * kSortBlock + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & mask], 1u);
+        k[it] = keys[idx < n ? idx : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t idx = base + it * kSortBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(uint32_t)(k[it] >> shift) & mask], 1u);
     }
     __syncthreads();
     if (threadIdx.x <= mask) hist[hist_index(threadIdx.x, blockIdx.x, nb, seg, (int)mask + 1)] = h[threadIdx.x];
@@ -105,12 +115,18 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const K *__res
     K key[kIt];
     uint32_t val[kIt], rank[kIt];
     const int64_t wbase = tile + (int64_t)wave * kPerWave;
+    // all loads first (see sort_hist_kernel), then the ranking
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t idx = wbase + it * 64 + lane;
+        const int64_t ci = idx < n ? idx : 0;
+        key[it] = kin[ci];
+        val[it] = vin[ci];
+    }
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
         const int64_t idx = wbase + it * 64 + lane;
         const bool valid = idx < n;
-        key[it] = valid ? kin[idx] : (K)0;
-        val[it] = valid ? vin[idx] : 0u;
         const uint32_t digit = (uint32_t)(key[it] >> shift) & mask;
         uint64_t peers = __ballot(valid);
 #pragma unroll
