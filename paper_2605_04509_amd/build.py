@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblfr.so")
-SOURCES = ["display.hip", "project.hip", "scan.hip", "sort.hip", "binning.hip", "blend.hip", "api.hip"]
+SOURCES = ["display.hip", "project.hip", "scan.hip", "sort.hip", "depth.hip", "binning.hip", "blend.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

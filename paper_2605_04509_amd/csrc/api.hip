@@ -23,10 +23,10 @@ constexpr int64_t kFirstChunkDiv = 64;
 namespace {
 
 enum Slot {
-    kRec, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kCountsSorted, kOffsets, kScanTemp,
+    kRec, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kWaveMask, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
-    kAliveSat, kItemBox, kNumSlots
+    kAliveSat, kItemBox, kNearK0, kNearV0, kNearK1, kNearV1, kSplit, kFarK0, kFarK1, kNumSlots
 };
 
 struct Buf {
@@ -387,14 +387,18 @@ lfr_status upload_tables(lfr_context *ctx, const lfr_display *d, const lfr_camer
 
 // Project every Gaussian for the clusters and views of `vt`, then sort each
 // cluster's Gaussians by depth (key = float32 depth bits, one sort segment
-// per cluster).
+// per cluster).  With R > 0 the depth order is split (depth.hip): only the
+// R nearest ranks of each cluster are sorted, the rest is the far chunk.
 struct Projected {
-    int64_t Mp = 0;             // stride of the depth-sorted per-cluster segments
+    int64_t Mp = 0;             // stride of the unsorted per-cluster key segments (dkey)
+    int64_t ns = 0;             // stride of the depth-sorted segments (dks, dvs)
     GaussRec *rec = nullptr;
     ushort4 *ibox = nullptr;
     float2 *mean2d = nullptr;
+    const uint32_t *dkey = nullptr;  // unsorted depth keys [K'][Mp]
     const uint32_t *dks = nullptr;
     const uint32_t *dvs = nullptr;
+    const uint32_t *thr = nullptr;   // split: [K'] far thresholds; else null
     int cbits = 0, tbits = 0;
 };
 
@@ -415,7 +419,7 @@ Grid make_grid(int W, int H, int tw, int th)
 Grid grid_of(const lfr_display *d) { return make_grid(d->W, d->H, d->tw, d->th); }
 
 lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *scene, const DevTables &dt,
-                            const ViewTables &vt, bool planes, Projected *out)
+                            const ViewTables &vt, bool planes, int64_t R, Projected *out)
 {
     const Grid *d = &d_;
     hipStream_t s = ctx->stream;
@@ -433,17 +437,21 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     // sort's granule, so the depth sort is a segmented sort on 32 bits
     const int64_t G = sort_segment_granule();
     const int64_t Mp = (M + G - 1) / G * G, MKp = Mp * KC;
+    const bool split = R > 0;
     ProjectOut po;
     po.Mp = Mp;
-    uint32_t *dkey1;
-    uint32_t *dval1;
+    uint32_t *dkey1 = nullptr;
+    uint32_t *dval1 = nullptr;
     void *sort_temp;
     CHK(ws_get_t(ctx, kRec, MK, &po.rec));
     CHK(ws_get_t(ctx, kItemBox, MK, &po.ibox));
     CHK(ws_get_t(ctx, kDKey0, MKp, &po.dkey));
-    CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
-    CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
-    CHK(ws_get_t(ctx, kDVal1, MKp, &dval1));
+    po.dval = nullptr;  // a split order needs no index array: items are read in index order
+    if (!split) {
+        CHK(ws_get_t(ctx, kDVal0, MKp, &po.dval));
+        CHK(ws_get_t(ctx, kDKey1, MKp, &dkey1));
+        CHK(ws_get_t(ctx, kDVal1, MKp, &dval1));
+    }
     // (the per-view mean planes only when something reads them)
     po.mean2d = nullptr;
     if (planes) CHK(ws_get_t(ctx, kMean2D, std::max<int64_t>(M * NV, 1), &po.mean2d));
@@ -454,13 +462,35 @@ lfr_status project_and_sort(lfr_context *ctx, const Grid &d_, const lfr_scene *s
     const size_t e1 = tm.mark(s);
     tm.span(kStProject, e0, e1);
     bool alt = false;
-    HIPCHK(ctx, radix_sort_u32(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, nullptr, nullptr, Mp));
+    out->thr = nullptr;
+    if (!split) {
+        HIPCHK(ctx, radix_sort_u32(po.dkey, po.dval, dkey1, dval1, MKp, 0, 32, sort_temp, &alt, s, nullptr, nullptr,
+                                   Mp));
+        out->dks = alt ? dkey1 : po.dkey;
+        out->dvs = alt ? dval1 : po.dval;
+        out->ns = Mp;
+    } else {
+        // the near set: at most R items per cluster, in segments of ns
+        const int64_t ns = (std::min<int64_t>(R, M) + G - 1) / G * G, nKs = ns * KC;
+        uint32_t *nk0, *nv0, *nk1, *nv1, *thr = nullptr;
+        void *split_temp;
+        CHK(ws_get_t(ctx, kNearK0, nKs, &nk0));
+        CHK(ws_get_t(ctx, kNearV0, nKs, &nv0));
+        CHK(ws_get_t(ctx, kNearK1, nKs, &nk1));
+        CHK(ws_get_t(ctx, kNearV1, nKs, &nv1));
+        CHK(ws_get(ctx, kSplit, split_temp_bytes(KC, Mp), &split_temp));
+        HIPCHK(ctx, launch_depth_split(po.dkey, KC, Mp, std::min<int64_t>(R, M), ns, split_temp, &thr, nk0, nv0, s));
+        HIPCHK(ctx, radix_sort_u32(nk0, nv0, nk1, nv1, nKs, 0, 32, sort_temp, &alt, s, nullptr, nullptr, ns));
+        out->dks = alt ? nk1 : nk0;
+        out->dvs = alt ? nv1 : nv0;
+        out->ns = ns;
+        out->thr = thr;
+    }
     tm.span(kStDepthSort, e1, tm.mark(s));
     out->rec = po.rec;
     out->ibox = po.ibox;
     out->mean2d = po.mean2d;
-    out->dks = alt ? dkey1 : po.dkey;
-    out->dvs = alt ? dval1 : po.dval;
+    out->dkey = po.dkey;
     out->cbits = cbits;
     out->tbits = tbits;
     out->Mp = Mp;
@@ -490,6 +520,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.ibox = ibox;
     bp.alive_total = nullptr;
     bp.alive_sat = nullptr;
+    bp.far_thr = nullptr;
     return bp;
 }
 
@@ -500,6 +531,19 @@ struct Totals {
     uint32_t alive;
     uint32_t pad;
 };
+
+// Start rank of the last depth chunk for M Gaussians and a first chunk of
+// len0 ranks (each next chunk 4x longer); 0 when there is only one chunk.
+int64_t last_chunk_start(int64_t M, int64_t len0)
+{
+    int64_t r0 = 0, len = len0;
+    for (;;) {
+        len = std::min(len, M - r0);
+        if (r0 + len >= M) return r0;
+        r0 += len;
+        len *= 4;
+    }
+}
 
 // One depth chunk: pair count -> scan -> (host readback) -> emit -> stable
 // sort on the tile bits -> list ranges.  With cap > 0 (a planned frame) there
@@ -513,20 +557,31 @@ struct Chunk {
     uint2 *ranges = nullptr;
 };
 
-lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr, int64_t r0, int64_t len,
-                     Totals *d_tot, Chunk *out, uint64_t cap = 0, uint64_t *d_need = nullptr)
+// far: the far chunk of a split depth order (items: every Gaussian in index
+// order, len = M; 64-bit pair keys with the depth below the list key).
+lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp_in, const Projected &pr, int64_t r0, int64_t len,
+                     Totals *d_tot, Chunk *out, uint64_t cap = 0, uint64_t *d_need = nullptr, bool far = false)
 {
+    BinParams bp = bp_in;
+    if (far) {
+        bp.Mp = pr.Mp;
+        bp.far_thr = pr.thr;
+    }
+    const uint32_t *dk = far ? pr.dkey : pr.dks;
     hipStream_t s = ctx->stream;
     Timer &tm = ctx->timer;
-    const int64_t n = len * bp.n_clusters;
-    uint32_t *counts, *offsets;
+    // per wavefront of 64 items: pair total, its exclusive scan, item mask
+    const int64_t nw = (len + 63) / 64 * bp.n_clusters;
+    uint32_t *wcnt, *woff;
+    uint64_t *wmask;
     void *scan_temp;
-    CHK(ws_get_t(ctx, kCounts, n, &counts));
-    CHK(ws_get_t(ctx, kOffsets, n, &offsets));
-    CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(n), &scan_temp));
+    CHK(ws_get_t(ctx, kCounts, nw, &wcnt));
+    CHK(ws_get_t(ctx, kOffsets, nw, &woff));
+    CHK(ws_get_t(ctx, kWaveMask, nw, &wmask));
+    CHK(ws_get(ctx, kScanTemp, scan_temp_bytes(nw), &scan_temp));
     const size_t e0 = tm.mark(s);
-    HIPCHK(ctx, launch_chunk_count(bp, pr.dks, pr.dvs, r0, len, counts, s));
-    HIPCHK(ctx, launch_exclusive_scan(counts, offsets, n, scan_temp, &d_tot->pairs, s));
+    HIPCHK(ctx, launch_chunk_count(bp, dk, pr.dvs, r0, len, wcnt, wmask, s, far));
+    HIPCHK(ctx, launch_exclusive_scan(wcnt, woff, nw, scan_temp, &d_tot->pairs, s));
     uint64_t P = cap;
     const uint64_t *dP = nullptr;
     Totals ht{};
@@ -544,28 +599,42 @@ lfr_status bin_chunk(lfr_context *ctx, const BinParams &bp, const Projected &pr,
                         (unsigned long long)ht.pairs);
         P = ht.pairs;
     }
-    uint32_t *pk0, *pv0, *pk1, *pv1;
+    uint32_t *pk0 = nullptr, *pv0, *pk1 = nullptr, *pv1;
+    uint64_t *fk0 = nullptr, *fk1 = nullptr;
     void *sort_temp;
-    CHK(ws_get_t(ctx, kPairK0, P, &pk0));
+    if (far) {
+        CHK(ws_get_t(ctx, kFarK0, P, &fk0));
+        CHK(ws_get_t(ctx, kFarK1, P, &fk1));
+    } else {
+        CHK(ws_get_t(ctx, kPairK0, P, &pk0));
+        CHK(ws_get_t(ctx, kPairK1, P, &pk1));
+    }
     CHK(ws_get_t(ctx, kPairV0, P, &pv0));
-    CHK(ws_get_t(ctx, kPairK1, P, &pk1));
     CHK(ws_get_t(ctx, kPairV1, P, &pv1));
-    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(bp.Mp * bp.n_clusters))),
+    CHK(ws_get(ctx, kSortTemp, sort_temp_bytes((int64_t)std::max<uint64_t>(P, (uint64_t)(pr.Mp * bp.n_clusters))),
                &sort_temp));
-    HIPCHK(ctx, launch_chunk_emit(bp, pr.dks, pr.dvs, r0, len, counts, offsets, P, pk0, pv0, s));
+    HIPCHK(ctx, launch_chunk_emit(bp, dk, pr.dvs, r0, len, wmask, woff, P, far ? (void *)fk0 : (void *)pk0, pv0, s,
+                                  far));
     const size_t e1 = tm.mark(s);
     tm.span(kStKeygen, e0, e1);
     bool palt = false;
-    HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, bp.cluster_bits, bp.cluster_bits + bits_for(
-                                   (int64_t)bp.TX * bp.TY), sort_temp, &palt, s, &tm, dP));
-    const uint32_t *keys = palt ? pk1 : pk0;
+    const int list_bits = bp.cluster_bits + bits_for((int64_t)bp.TX * bp.TY);
+    if (far)
+        HIPCHK(ctx, radix_sort_u64(fk0, pv0, fk1, pv1, (int64_t)P, 0, 32 + list_bits, sort_temp, &palt, s, 0, &tm,
+                                   dP));
+    else
+        HIPCHK(ctx, radix_sort_u32(pk0, pv0, pk1, pv1, (int64_t)P, bp.cluster_bits, list_bits, sort_temp, &palt, s,
+                                   &tm, dP));
     const size_t e2 = tm.mark(s);
     tm.span(kStSort, e1, e2);
     const int64_t n_ranges = ((int64_t)bp.TX * bp.TY) << bp.cluster_bits;
     uint2 *ranges;
     CHK(ws_get_t(ctx, kRanges, n_ranges, &ranges));
     HIPCHK(ctx, launch_fill_u32((uint32_t *)ranges, 0u, 2 * n_ranges, s));
-    HIPCHK(ctx, launch_ranges(keys, (int64_t)P, ranges, s, dP));
+    if (far)
+        HIPCHK(ctx, launch_ranges_u64(palt ? fk1 : fk0, (int64_t)P, ranges, s, dP));
+    else
+        HIPCHK(ctx, launch_ranges(palt ? pk1 : pk0, (int64_t)P, ranges, s, dP));
     tm.span(kStRanges, e2, tm.mark(s));
     out->P = cap > 0 ? 0 : P;
     out->alive = ht.alive;
@@ -857,7 +926,15 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
     // means do not fit in the record
     bool planes = !remap;
     for (int k = 0; k < vt.n_clusters; ++k) planes = planes || vt.cv_off[k + 1] - vt.cv_off[k] > kItemViews;
-    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, planes, &pr));
+    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x
+    // from len0.  With more than one chunk and no lists to keep, the depth
+    // order is split: only the ranks before the last chunk are sorted, and
+    // the last chunk is the far set, binned in index order.
+    const int64_t len0 = opts->first_chunk > 0
+                             ? (int64_t)opts->first_chunk
+                             : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
+    const int64_t R = save ? 0 : last_chunk_start(M, len0);
+    CHK(project_and_sort(ctx, grid_of(d), scene, dt, vt, planes, R, &pr));
 
     // traversal state: unsaturated subpixels per (tile, cluster) list and in
     // total, the lists' alive bits, per-subpixel (T, C), per-item flags
@@ -918,19 +995,15 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
         CHK(ws_get_t(ctx, kSaveT, nsub, &bp.save_T));
         CHK(ws_get_t(ctx, kSaveEnd, nsub, &bp.save_end));
     }
-    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.rec, pr.ibox);
+    BinParams bin = bin_params(grid_of(d), dt, vt, M, pr.ns, pr.cbits, alive_bits, pr.rec, pr.ibox);
     if (planned) bin.alive_total = &d_tot->alive;
 
 
-    // depth chunks: ranks [r0, r0 + len) of every cluster, len growing 4x.
     // The backward needs each subpixel's whole list in one chunk: a render
     // that keeps its lists first tries the first chunk alone and keeps it if
     // every subpixel saturated there (the lists then hold every entry any
     // subpixel reached); otherwise it renders again with one chunk holding
     // every rank.
-    const int64_t len0 = opts->first_chunk > 0
-                             ? (int64_t)opts->first_chunk
-                             : std::max<int64_t>(kFirstChunk, (M + kFirstChunkDiv - 1) / kFirstChunkDiv);
     int64_t r0 = 0, len = len0;
     Chunk saved_chunk;
     bool blend_ran = false;
@@ -941,13 +1014,16 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
         if (single && c == 0) len = std::max<int64_t>(M, 1);
         len = std::min(len, M - r0);
         const bool last = r0 + len >= M;
+        // the far chunk: every Gaussian, in index order, beyond the thresholds
+        const bool far = pr.thr && r0 >= R;
+        const int64_t cr0 = far ? 0 : r0, clen = far ? M : len;
         Chunk ch;
         if (planned) {
             const uint64_t cap = c < (int)run->caps->size() ? (*run->caps)[c] : kUnplannedChunkCap;
-            CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch, std::max<uint64_t>(cap, 1),
-                          run->d_need ? run->d_need + std::min(c, kMaxPlannedChunks - 1) : nullptr));
+            CHK(bin_chunk(ctx, bin, pr, cr0, clen, d_tot, &ch, std::max<uint64_t>(cap, 1),
+                          run->d_need ? run->d_need + std::min(c, kMaxPlannedChunks - 1) : nullptr, far));
         } else {
-            CHK(bin_chunk(ctx, bin, pr, r0, len, d_tot, &ch));
+            CHK(bin_chunk(ctx, bin, pr, cr0, clen, d_tot, &ch, 0, nullptr, far));
             if (run && run->chunk_pairs) run->chunk_pairs->push_back(ch.P);
         }
         saved_chunk = ch;
@@ -1455,14 +1531,14 @@ lfr_status lfr_render_fullframe_interlace(lfr_context *ctx, const lfr_display *d
         DevTables dt;
         CHK(upload_tables(ctx, d, &host_cams, vt, &dt));
         Projected pr;
-        CHK(project_and_sort(ctx, fg, scene, dt, vt, true, &pr));
+        CHK(project_and_sort(ctx, fg, scene, dt, vt, true, 0, &pr));
         // one chunk with every tile of every view alive
         uint32_t *alive_bits;
         Totals *d_tot;
         CHK(ws_get_t(ctx, kAliveBits, (int64_t)B * fg.TY * words, &alive_bits));
         CHK(ws_get_t(ctx, kTotal, 1, &d_tot));
         HIPCHK(ctx, launch_fill_u32(alive_bits, 0xFFFFFFFFu, (int64_t)B * fg.TY * words, s));
-        const BinParams bin = bin_params(fg, dt, vt, M, pr.Mp, pr.cbits, alive_bits, pr.rec, pr.ibox);
+        const BinParams bin = bin_params(fg, dt, vt, M, pr.ns, pr.cbits, alive_bits, pr.rec, pr.ibox);
         Chunk ch;
         CHK(bin_chunk(ctx, bin, pr, 0, M, d_tot, &ch));
         pairs += ch.P;

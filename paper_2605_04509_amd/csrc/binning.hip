@@ -14,6 +14,9 @@
 //
 // Tile coverage is conservative (the box bounds the alpha >= 1/255 region
 // with margins), so the rendered result does not depend on the tiling.
+#include <algorithm>
+#include <type_traits>
+
 #include "lfr_internal.h"
 
 namespace lfr {
@@ -204,35 +207,42 @@ __device__ inline int wave_search(uint32_t key, uint32_t x)
 
 // Items of one chunk: depth ranks [r0, r0 + len) of every cluster; item
 // (k, r) sits at k * Mp + r of the depth-sorted arrays and at k * len + (r - r0)
-// of the chunk's count / offset arrays.
+// of the chunk's count / offset arrays.  The far chunk (kFar) is the last
+// chunk of a split depth order: its items are every Gaussian r < len = M in
+// index order, read from the unsorted key array at k * Mp + r, those with a
+// valid key >= far_thr[k] taking part; its pair keys are 64-bit, the
+// (tile, cluster) key above the depth key, so that one stable sort orders
+// each list by (depth, i).
 //
 // Load balancing: each wavefront enumerates the units of its 64 consecutive
 // items in item order and hands them out 64 at a time, so an item covering
 // thousands of tiles is spread over the whole wavefront.  The counting pass
-// adds each unit's tile count to its item (LDS); the emitting pass lays the
-// wavefront's pairs out contiguously (its items' offsets are consecutive)
-// and writes them with consecutive lanes on consecutive slots.
-template <bool kEmit>
-__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const uint32_t *__restrict__ dkey_sorted,
-                                                           const uint32_t *__restrict__ dval_sorted, int64_t r0,
-                                                           int64_t len, uint32_t *__restrict__ counts,
-                                                           const uint32_t *__restrict__ offsets, uint64_t n_pairs,
-                                                           uint32_t *__restrict__ pair_keys,
-                                                           uint32_t *__restrict__ pair_vals)
+// adds each unit's tile count to its item (LDS) and writes, per wavefront w
+// (k * ceil(len / 64) + r / 64), its pair total wcnt[w] and the mask of its
+// items with pairs wmask[w]; the emitting pass starts at the wavefront's
+// slot woff[w] (the exclusive scan of wcnt), lays the wavefront's pairs out
+// in item order and writes them with consecutive lanes on consecutive
+// slots.  A wavefront whose mask is empty emits nothing and reads no item.
+// One run of 64 items (run wk of cluster k, run w of the chunk) on one
+// wavefront; s_cnt: the wavefront's 64 counters in LDS.
+template <bool kEmit, bool kFar>
+__device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *__restrict__ dkey_sorted,
+                                          const uint32_t *__restrict__ dval_sorted, int64_t r0, int64_t len, int k,
+                                          int64_t wk, int64_t w, uint32_t *__restrict__ wcnt,
+                                          uint64_t *__restrict__ wmask, const uint32_t *__restrict__ woff,
+                                          uint64_t n_pairs, void *__restrict__ pair_keys_v,
+                                          uint32_t *__restrict__ pair_vals, uint32_t *s_cnt)
 {
-    __shared__ uint32_t s_cnt[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t rl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
+    using PairKey = typename std::conditional<kFar, uint64_t, uint32_t>::type;
+    PairKey *pair_keys = (PairKey *)pair_keys_v;
+    const int lane = threadIdx.x & 63;
+    const int64_t rl = wk * 64 + lane;
     const bool in = rl < len;
-    const int64_t o = (int64_t)k * len + rl;
-    // every subpixel saturated (chunks planned ahead of time): no pairs
-    if (bp.alive_total && *bp.alive_total == 0u) {
-        if (!kEmit && in) counts[o] = 0u;
-        return;
-    }
+    // the emitting pass: only the items the counting pass found pairs for
+    const uint64_t wm = kEmit ? wmask[w] : ~0ull;
+    if (kEmit && wm == 0ull) return;
     const GaussRec *items_k = bp.items + (int64_t)k * bp.M;
-    uint32_t i = 0;
+    uint32_t i = 0, dkey_own = 0;
     int U = 0;
     GaussRec own = {};  // this lane's item record and union tile box (when it has units)
     ushort4 obox = make_ushort4(0, 0, 0, 0);
@@ -240,21 +250,23 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     // nothing (the summed-area table's total)
     const bool cluster_alive =
         !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
-    if (in && cluster_alive) {
+    if (in && cluster_alive && ((wm >> lane) & 1ull)) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
-        // key, index and (emitting pass) count are loaded together; the
-        // emitting pass skips items the counting pass found empty without
-        // reading their records: most items of late chunks
-        const uint32_t dk = dkey_sorted[e], dv = dval_sorted[e];
-        const uint32_t cnt = kEmit ? counts[o] : 1u;
+        const uint32_t dk = dkey_sorted[e], dv = kFar ? (uint32_t)rl : dval_sorted[e];
+        // (far items sit at their index: the box is loaded with the key)
+        ushort4 fbox = make_ushort4(0, 0, 0, 0);
+        if (kFar) fbox = bp.ibox[(int64_t)k * bp.M + rl];
         // (the index is tested too, though never all ones, so that its load
         // is issued with the key's instead of after the key is known)
-        if ((dk != 0xFFFFFFFFu) & (cnt != 0u) & (dv != 0xFFFFFFFFu)) {
+        bool take = (dk != 0xFFFFFFFFu) & (dv != 0xFFFFFFFFu);
+        if (kFar) take = take & (dk >= bp.far_thr[k]);
+        if (take) {
             i = dv;
+            dkey_own = dk;
             // items whose tiles are all saturated emit nothing: the counting
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
-            obox = bp.ibox[(int64_t)k * bp.M + i];
+            obox = kFar ? fbox : bp.ibox[(int64_t)k * bp.M + i];
             if (kEmit || !bp.alive_sat || rect_alive(bp, k, obox)) {
                 own = items_k[i];
                 U = item_units(obox);
@@ -264,14 +276,15 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);
     const uint32_t ubase = uincl - (uint32_t)U;
     const uint32_t utot = (uint32_t)__shfl((int)uincl, 63, 64);
-    if (!kEmit) s_cnt[wave][lane] = 0;
+    if (!kEmit) s_cnt[lane] = 0;
     uint64_t out = 0;  // next pair slot of this wavefront
-    if (kEmit && utot > 0) out = (uint64_t)offsets[(int64_t)k * len + (rl - lane)];
+    if (kEmit && utot > 0) out = (uint64_t)woff[w];
     for (uint32_t ub = 0; ub < utot; ub += 64) {
         const uint32_t u = ub + (uint32_t)lane;
         const bool has = u < utot;
         const int owner = wave_search(ubase, has ? u : utot - 1);
         const uint32_t iown = (uint32_t)__shfl((int)i, owner, 64);
+        const uint32_t down = kFar ? (uint32_t)__shfl((int)dkey_own, owner, 64) : 0u;
         const uint32_t uloc = (has ? u : utot - 1) - (uint32_t)__shfl((int)ubase, owner, 64);
         int ty = 0, w = 0;
         uint32_t m = 0;
@@ -280,7 +293,7 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
         if (has) m = unit_mask(bp, k, iown, rown, bown, (int)uloc, ty, w);
         const uint32_t c = (uint32_t)__popc(m);
         if (!kEmit) {
-            if (c) atomicAdd(&s_cnt[wave][owner], c);
+            if (c) atomicAdd(&s_cnt[owner], c);
         } else {
             // spread this round's pairs over the lanes
             const uint32_t cincl = wave_incl_scan(c, lane);
@@ -295,17 +308,61 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
                 const uint32_t kth = px - (uint32_t)__shfl((int)cbase, q, 64);
                 const uint32_t tb = (uint32_t)__shfl((int)tilebase, q, 64);
                 const uint32_t iq = (uint32_t)__shfl((int)iown, q, 64);
+                const uint32_t dq = kFar ? (uint32_t)__shfl((int)down, q, 64) : 0u;
                 const uint64_t slot = out + pidx;
                 if (pidx < ctot && slot < n_pairs) {
                     const uint32_t t = tb + (uint32_t)select_bit(mq, (int)kth);
-                    pair_keys[slot] = (t << bp.cluster_bits) | (uint32_t)k;
+                    const uint32_t list = (t << bp.cluster_bits) | (uint32_t)k;
+                    if (kFar)
+                        pair_keys[slot] = (PairKey)(((uint64_t)list << 32) | dq);
+                    else
+                        pair_keys[slot] = (PairKey)list;
                     pair_vals[slot] = iq;
                 }
             }
             out += ctot;
         }
     }
-    if (!kEmit && in) counts[o] = s_cnt[wave][lane];
+    if (!kEmit) {
+        const uint32_t c = s_cnt[lane];
+        const uint64_t m = __ballot(c != 0u);
+        const uint32_t tot = (uint32_t)__shfl((int)wave_incl_scan(c, lane), 63, 64);
+        if (lane == 0) {
+            wcnt[w] = tot;
+            wmask[w] = m;
+        }
+    }
+}
+
+// Wavefronts take the chunk's runs of 64 items in turn (run w = k *
+// ceil(len / 64) + r / 64), so a long chunk runs on a few thousand blocks.
+template <bool kEmit, bool kFar>
+__global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const uint32_t *__restrict__ dkey_sorted,
+                                                           const uint32_t *__restrict__ dval_sorted, int64_t r0,
+                                                           int64_t len, uint32_t *__restrict__ wcnt,
+                                                           uint64_t *__restrict__ wmask,
+                                                           const uint32_t *__restrict__ woff, uint64_t n_pairs,
+                                                           void *__restrict__ pair_keys_v,
+                                                           uint32_t *__restrict__ pair_vals)
+{
+    __shared__ uint32_t s_cnt[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // (run counts fit 32 bits: K' M < 2^32 items)
+    const uint32_t nwk = (uint32_t)((len + 63) >> 6), nw = nwk * (uint32_t)bp.n_clusters;
+    // every subpixel saturated (chunks planned ahead of time): no pairs
+    const bool done = bp.alive_total && *bp.alive_total == 0u;
+    for (uint32_t w = blockIdx.x * 4u + (uint32_t)wave; w < nw; w += gridDim.x * 4u) {
+        const uint32_t k = w / nwk;
+        if (done) {
+            if (!kEmit && lane == 0) {
+                wcnt[w] = 0u;
+                wmask[w] = 0ull;
+            }
+            continue;
+        }
+        chunk_run<kEmit, kFar>(bp, dkey_sorted, dval_sorted, r0, len, (int)k, (int64_t)(w - k * nwk), (int64_t)w,
+                               wcnt, wmask, woff, n_pairs, pair_keys_v, pair_vals, s_cnt[wave]);
+    }
 }
 
 __global__ void __launch_bounds__(256) fill_kernel(uint32_t *p, uint32_t v, int64_t n)
@@ -321,18 +378,24 @@ __global__ void __launch_bounds__(256) copy_kernel(uint32_t *__restrict__ dst, c
         dst[s] = src[s];
 }
 
+// The (tile, cluster) list of a pair key: the key itself, or the upper half
+// of a far-chunk key (list above depth).
+__device__ __forceinline__ uint32_t list_of(uint32_t key) { return key; }
+__device__ __forceinline__ uint32_t list_of(uint64_t key) { return (uint32_t)(key >> 32); }
+
 // [start, end) of every (tile, cluster) list, indexed by the list's key.  The
 // pair count is P, or min(*dP, P) when dP is given.
-__global__ void __launch_bounds__(256) ranges_kernel(const uint32_t *__restrict__ keys, int64_t P_cap,
+template <typename K>
+__global__ void __launch_bounds__(256) ranges_kernel(const K *__restrict__ keys, int64_t P_cap,
                                                       const uint64_t *dP, uint2 *ranges)
 {
     const int64_t P = dP ? (int64_t)min(*dP, (uint64_t)P_cap) : P_cap;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     // the three loads are independent (clamped indices), so none waits for another
-    const uint32_t k = keys[p];
-    const uint32_t kb = keys[p > 0 ? p - 1 : p];
-    const uint32_t ka = keys[p + 1 < P ? p + 1 : p];
+    const uint32_t k = list_of(keys[p]);
+    const uint32_t kb = list_of(keys[p > 0 ? p - 1 : p]);
+    const uint32_t ka = list_of(keys[p + 1 < P ? p + 1 : p]);
     if (p == 0 || kb != k) ranges[k].x = (uint32_t)p;
     if (p == P - 1 || ka != k) ranges[k].y = (uint32_t)(p + 1);
 }
@@ -409,24 +472,47 @@ __global__ void __launch_bounds__(256) alive_sat_kernel(const uint32_t *__restri
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Blocks of 4 wavefronts for a chunk of len ranks per cluster: one per 4
+// runs of 64 items, at most kChunkBlocks.
+constexpr int64_t kChunkBlocks = 4096;
+static unsigned chunk_blocks(int64_t len, int n_clusters)
+{
+    const int64_t runs = (len + 63) / 64 * n_clusters;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((runs + 3) / 4, kChunkBlocks));
+}
+
 hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                              int64_t r0, int64_t len, uint32_t *counts, hipStream_t s)
+                              int64_t r0, int64_t len, uint32_t *wcnt, uint64_t *wmask, hipStream_t s, bool far)
 {
     if (len == 0 || bp.n_clusters == 0) return hipSuccess;
-    hipLaunchKernelGGL(chunk_tiles_kernel<false>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp,
-                       dkey_sorted, dval_sorted, r0, len, counts, (const uint32_t *)nullptr, (uint64_t)0,
-                       (uint32_t *)nullptr, (uint32_t *)nullptr);
+    if (far && !bp.far_thr) return hipErrorInvalidValue;
+    const dim3 grid(chunk_blocks(len, bp.n_clusters));
+    if (far)
+        hipLaunchKernelGGL((chunk_tiles_kernel<false, true>), grid, dim3(256), 0, s, bp, dkey_sorted, dval_sorted,
+                           r0, len, wcnt, wmask, (const uint32_t *)nullptr, (uint64_t)0, (void *)nullptr,
+                           (uint32_t *)nullptr);
+    else
+        hipLaunchKernelGGL((chunk_tiles_kernel<false, false>), grid, dim3(256), 0, s, bp, dkey_sorted, dval_sorted,
+                           r0, len, wcnt, wmask, (const uint32_t *)nullptr, (uint64_t)0, (void *)nullptr,
+                           (uint32_t *)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                             int64_t r0, int64_t len, const uint32_t *counts, const uint32_t *offsets,
-                             uint64_t n_pairs, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s)
+                             int64_t r0, int64_t len, const uint64_t *wmask, const uint32_t *woff,
+                             uint64_t n_pairs, void *pair_keys, uint32_t *pair_vals, hipStream_t s, bool far)
 {
     if (len == 0 || bp.n_clusters == 0 || n_pairs == 0) return hipSuccess;
-    hipLaunchKernelGGL(chunk_tiles_kernel<true>, dim3(blocks_for(len), bp.n_clusters), dim3(256), 0, s, bp,
-                       dkey_sorted, dval_sorted, r0, len, const_cast<uint32_t *>(counts), offsets, n_pairs,
-                       pair_keys, pair_vals);
+    if (far && !bp.far_thr) return hipErrorInvalidValue;
+    const dim3 grid(chunk_blocks(len, bp.n_clusters));
+    if (far)
+        hipLaunchKernelGGL((chunk_tiles_kernel<true, true>), grid, dim3(256), 0, s, bp, dkey_sorted, dval_sorted, r0,
+                           len, (uint32_t *)nullptr, const_cast<uint64_t *>(wmask), woff, n_pairs, pair_keys,
+                           pair_vals);
+    else
+        hipLaunchKernelGGL((chunk_tiles_kernel<true, false>), grid, dim3(256), 0, s, bp, dkey_sorted, dval_sorted,
+                           r0, len, (uint32_t *)nullptr, const_cast<uint64_t *>(wmask), woff, n_pairs, pair_keys,
+                           pair_vals);
     return hipGetLastError();
 }
 
@@ -442,7 +528,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s, const uint64_t *dP)
 {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(P)), dim3(256), 0, s, keys, P, dP, ranges);
+    hipLaunchKernelGGL(ranges_kernel<uint32_t>, dim3(blocks_for(P)), dim3(256), 0, s, keys, P, dP, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges_u64(const uint64_t *keys, int64_t P, uint2 *ranges, hipStream_t s, const uint64_t *dP)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(ranges_kernel<uint64_t>, dim3(blocks_for(P)), dim3(256), 0, s, keys, P, dP, ranges);
     return hipGetLastError();
 }
 

@@ -188,7 +188,7 @@ struct ProjectOut {
     GaussRec *rec;      // [K'][M]
     ushort4 *ibox;      // [K'][M]  the records' union tile boxes (read alone to skip saturated items)
     uint32_t *dkey;     // [K'][Mp] float32 depth bits, 0xFFFFFFFF if invalid or padding
-    uint32_t *dval;     // [K'][Mp] Gaussian index
+    uint32_t *dval;     // [K'][Mp] Gaussian index; null: not written (a split depth order implies it)
     float2 *mean2d;     // [N'][M]  (kFarMean, kFarMean) if the mean is invalid; null: not written
     int64_t Mp;         // M rounded up to the sort's segment granule
 };
@@ -224,8 +224,20 @@ hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1
 // seg_len > 0: a segmented sort of n / seg_len independent segments of
 // seg_len keys each (seg_len a multiple of sort_segment_granule()).
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n,
-                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s, int64_t seg_len = 0);
+                          int b0, int b1, void *temp, bool *result_in_alt, hipStream_t s, int64_t seg_len = 0,
+                          Timer *tm = nullptr, const uint64_t *dn = nullptr);
 int64_t sort_segment_granule();
+
+// Split depth order (depth.hip): thresholds thr[k] (returned in *thr_out,
+// inside temp) with at most R valid keys of cluster k's segment of dkey
+// ([K'][Mp]) below them, and the keys below, in index order with their
+// Gaussian index as value, copied into cluster k's segment of near_key /
+// near_val ([K'][ncap], the rest of each segment invalid keys).  Mp and ncap
+// are multiples of sort_segment_granule(), R <= ncap.
+size_t split_temp_bytes(int n_clusters, int64_t Mp);
+hipError_t launch_depth_split(const uint32_t *dkey, int n_clusters, int64_t Mp, int64_t R, int64_t ncap,
+                              void *temp, uint32_t **thr_out, uint32_t *near_key, uint32_t *near_val,
+                              hipStream_t s);
 
 struct BinParams {
     int64_t M;
@@ -241,17 +253,27 @@ struct BinParams {
     const ushort4 *ibox;      // [K'][M] union tile box of each record
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
+    const uint32_t *far_thr;      // [K'] depth-key thresholds of the far chunk (split depth order), or null
 };
+// Per wavefront of 64 items (K' * ceil(len / 64) of them): pair total wcnt
+// and mask of the items with pairs wmask.  far: the far chunk of a split
+// depth order (dkey_sorted is then the unsorted key array, dval_sorted
+// unused, pair keys 64-bit).
 hipError_t launch_chunk_count(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                              int64_t r0, int64_t len, uint32_t *counts, hipStream_t s);
-// counts: the counting pass's per-item pair counts (items with none are skipped).
+                              int64_t r0, int64_t len, uint32_t *wcnt, uint64_t *wmask, hipStream_t s,
+                              bool far = false);
+// wmask from the counting pass; woff: the exclusive scan of its wcnt.
 hipError_t launch_chunk_emit(const BinParams &bp, const uint32_t *dkey_sorted, const uint32_t *dval_sorted,
-                             int64_t r0, int64_t len, const uint32_t *counts, const uint32_t *offsets,
-                             uint64_t n_pairs, uint32_t *pair_keys, uint32_t *pair_vals, hipStream_t s);
+                             int64_t r0, int64_t len, const uint64_t *wmask, const uint32_t *woff,
+                             uint64_t n_pairs, void *pair_keys, uint32_t *pair_vals, hipStream_t s,
+                             bool far = false);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // With dP, the pair count is min(*dP, P) read on the device (P sizes the grid).
 hipError_t launch_ranges(const uint32_t *keys, int64_t P, uint2 *ranges, hipStream_t s,
                          const uint64_t *dP = nullptr);
+// The same for the far chunk's 64-bit keys (list in the upper half).
+hipError_t launch_ranges_u64(const uint64_t *keys, int64_t P, uint2 *ranges, hipStream_t s,
+                             const uint64_t *dP = nullptr);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
 hipError_t launch_record_count(const uint64_t *src, uint64_t *dst, hipStream_t s);
 hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int cluster_bits, uint32_t *sat,

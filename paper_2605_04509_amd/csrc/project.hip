@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         if (i < Mp)
             for (int k = 0; k < n_clusters; ++k) {
                 out.dkey[(int64_t)k * Mp + i] = 0xFFFFFFFFu;
-                out.dval[(int64_t)k * Mp + i] = 0u;
+                if (out.dval) out.dval[(int64_t)k * Mp + i] = 0u;
             }
         return;
     }
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(SceneDev sc, const 
         FullProj f = {};
         if (want_cov && m.valid) f = project_full<DEG>(c, m, S, mx, my, mz, tau_o, shc);
         const int64_t idx = (int64_t)k * M + i, kidx = (int64_t)k * Mp + i;
-        out.dval[kidx] = (uint32_t)i;
+        if (out.dval) out.dval[kidx] = (uint32_t)i;
         // the cluster's views: mean planes, the record's means (the first
         // kItemViews views, placed by selects rather than a dynamic index so
         // that the record stays in registers), and the union of the tile

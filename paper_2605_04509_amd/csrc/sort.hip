@@ -233,10 +233,10 @@ hipError_t radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1
 }
 
 hipError_t radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int b0, int b1,
-                          void *temp, bool *in_alt, hipStream_t s, int64_t seg_len)
+                          void *temp, bool *in_alt, hipStream_t s, int64_t seg_len, Timer *tm, const uint64_t *dn)
 {
     if (seg_len > 0 && (seg_len % kSortTile != 0 || n % seg_len != 0)) return hipErrorInvalidValue;
-    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, nullptr, nullptr,
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, b0, b1, temp, in_alt, s, tm, dn,
                                      seg_len > 0 ? seg_len / kSortTile : 0);
 }
 

@@ -221,6 +221,40 @@ def test_depth_chunking_does_not_change_the_image(lib, tiny_setup, S, remap):
     d.close()
 
 
+def test_equal_depths_keep_index_order_across_depth_chunks(lib, tiny_setup):
+    """Every Gaussian of the tiny scene gets a twin at the same mean (hence the
+    same depth in every cluster) but with another colour and opacity, so the
+    blend order of equal depths decides the image.  Rendered in several depth
+    chunks (only the ranks before the last chunk depth-sorted, the last chunk
+    binned in index order and sorted with the depth in its pair keys), the
+    image must be bit-identical to one chunk from a single full depth sort,
+    and that one must match the oracle, which orders equal depths by index."""
+    lfr, ctx = lib
+    w, scene, cams, V, _ = tiny_setup
+    rng = np.random.default_rng(11)
+    perm = rng.permutation(scene.num_gaussians)
+    twin = Scene(scene.means.copy(), scene.log_scales[perm].copy(), scene.quats[perm].copy(),
+                 scene.opacities[perm].copy(), scene.sh[perm].copy(), scene.sh_degree)
+    both = Scene(*(np.concatenate([a, b]) for a, b in zip(
+        (scene.means, scene.log_scales, scene.quats, scene.opacities, scene.sh),
+        (twin.means, twin.log_scales, twin.quats, twin.opacities, twin.sh))), scene.sh_degree)
+    ds = lfr.DeviceScene.from_numpy(both)
+    d = _display(lfr, ctx, w.display)
+    for S in (1, 4):
+        whole = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=1 << 20)
+        assert ctx.stats()["chunks"] == 1
+        if S == 4:
+            r = oracle.render_frame_ranged(both, cams, w.display, V, S)
+            say(compare(whole, r, colour_bound(both), label="twins S=4"))
+        for fc in (1, 5, 64):
+            img = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=fc)
+            st = ctx.stats()
+            say("twins S =", S, "first chunk", fc, "chunks", st["chunks"], "pairs", st["pairs"])
+            assert st["chunks"] > 1
+            np.testing.assert_array_equal(img, whole)
+    d.close()
+
+
 @pytest.mark.parametrize("S,first_chunk", [(1, 0), (4, 0), (4, 64), (8, 7)])
 def test_work_counts_agree_across_blend_orders(lib, tiny_setup, S, first_chunk):
     """The counting renders report the method's work on the binned lists: the
