@@ -1046,8 +1046,8 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
             tm.span(kStBlend, e0, e1);
             ++ctx->stats.blend_launches;
             if (!last) {
-                HIPCHK(ctx, launch_alive_bits(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits, s));
-                HIPCHK(ctx, launch_alive_sat(tc_alive, vt.n_clusters, d->TX, d->TY, pr.cbits, alive_sat, s));
+                HIPCHK(ctx, launch_alive_tables(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits,
+                                                alive_sat, s));
                 bin.alive_sat = alive_sat;   // later chunks skip items whose tiles are all saturated
                 tm.span(kStRanges, e1, tm.mark(s));
             }

@@ -470,6 +470,55 @@ __global__ void __launch_bounds__(256) alive_sat_kernel(const uint32_t *__restri
     }
 }
 
+// Both tables of one cluster at once, the summed-area table built in LDS
+// (for grids whose table fits kSatLdsMax entries): each wavefront takes tile
+// rows, 64 tiles at a time; the ballot of the row's alive flags gives two
+// words of alive bits, their prefix sum the table's row; the columns are then
+// prefixed in LDS by one thread each and the table written out whole.
+constexpr int kSatBlock = 1024;
+constexpr int kSatLdsMax = 12288;  // 48 KB
+__global__ void __launch_bounds__(kSatBlock) alive_tables_kernel(const uint32_t *__restrict__ tc_alive, int TX,
+                                                                  int TY, int words, int cluster_bits,
+                                                                  uint32_t *__restrict__ bits,
+                                                                  uint32_t *__restrict__ sat)
+{
+    __shared__ uint32_t S[kSatLdsMax];
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pitch = TX + 1, n = (TY + 1) * pitch;
+    for (int x = threadIdx.x; x <= TX; x += kSatBlock) S[x] = 0u;
+    for (int ty = wave; ty < TY; ty += kSatBlock / 64) {
+        uint32_t *row = S + (ty + 1) * pitch;
+        if (lane == 0) row[0] = 0u;
+        uint32_t carry = 0;
+        for (int x0 = 0; x0 < TX; x0 += 64) {
+            const int tx = x0 + lane;
+            const uint32_t t = (uint32_t)(ty * TX + min(tx, TX - 1));
+            const uint32_t c = tc_alive[(t << cluster_bits) | (uint32_t)k];
+            const uint32_t v = (tx < TX && c > 0u) ? 1u : 0u;
+            const uint64_t b = __ballot(v != 0u);
+            const int w0 = x0 >> 5;
+            uint32_t *brow = bits + ((int64_t)k * TY + ty) * words;
+            if (lane == 0) brow[w0] = (uint32_t)b;
+            if (lane == 1 && w0 + 1 < words) brow[w0 + 1] = (uint32_t)(b >> 32);
+            const uint32_t incl = wave_incl_scan(v, lane);
+            if (tx < TX) row[tx + 1] = carry + incl;
+            carry += (uint32_t)__popcll(b);
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x <= TX; x += kSatBlock) {
+        uint32_t run = 0;
+        for (int y = 1; y <= TY; ++y) {
+            run += S[y * pitch + x];
+            S[y * pitch + x] = run;
+        }
+    }
+    __syncthreads();
+    uint32_t *out = sat + (int64_t)k * n;
+    for (int e = threadIdx.x; e < n; e += kSatBlock) out[e] = S[e];
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // Blocks of 4 wavefronts for a chunk of len ranks per cluster: one per 4
@@ -560,6 +609,20 @@ hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, in
     if (n_clusters == 0) return hipSuccess;
     hipLaunchKernelGGL(alive_sat_kernel, dim3((unsigned)n_clusters), dim3(256), 0, s, tc_alive, TX, TY, cluster_bits,
                        sat);
+    return hipGetLastError();
+}
+
+hipError_t launch_alive_tables(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words, int cluster_bits,
+                               uint32_t *bits, uint32_t *sat, hipStream_t s)
+{
+    if (n_clusters == 0) return hipSuccess;
+    if ((int64_t)(TY + 1) * (TX + 1) > kSatLdsMax) {
+        const hipError_t e = launch_alive_bits(tc_alive, n_clusters, TX, TY, words, cluster_bits, bits, s);
+        if (e != hipSuccess) return e;
+        return launch_alive_sat(tc_alive, n_clusters, TX, TY, cluster_bits, sat, s);
+    }
+    hipLaunchKernelGGL(alive_tables_kernel, dim3((unsigned)n_clusters), dim3(kSatBlock), 0, s, tc_alive, TX, TY, words,
+                       cluster_bits, bits, sat);
     return hipGetLastError();
 }
 

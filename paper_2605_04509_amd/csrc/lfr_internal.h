@@ -280,6 +280,10 @@ hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, in
                             hipStream_t s);
 hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
                              int cluster_bits, uint32_t *bits, hipStream_t s);
+// Both: the alive bits and the summed-area table, in one launch where the
+// table fits in LDS.
+hipError_t launch_alive_tables(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
+                               int cluster_bits, uint32_t *bits, uint32_t *sat, hipStream_t s);
 hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,
                            int cluster_bits, uint32_t *counts, hipStream_t s);
 
