@@ -161,7 +161,10 @@ def stage_roofline(work, stages, M, deg, n_tiles, n_sub, frame_s):
       keygen     B = M (28 K' + 8 N') + 12 P
       sort       B = 24 P ceil((32 + bits(K') + bits(T)) / 8)   (one stable sort of the
                  (tile, cluster, depth) keys with 8-bit digits; the design's own passes
-                 are a 4-pass depth sort of the M K' items plus 2 tile-bit passes per chunk)
+                 are three passes over the M K' depth keys that split off the near set, a
+                 4-pass sort of the near set (at most R items per cluster, R the start rank
+                 of the last chunk), 2 tile-bit passes per ranked chunk and one 64-bit sort
+                 of the last chunk's pairs)
       ranges     B = 8 P + 8 T K'
       blend      B = P (36 + 8 N'/K') + 10 n_sub              O = 14 n_eval
     roofline time = max(B / 8 TB/s, O / 39.3 T lane-ops/s); fraction = roofline
