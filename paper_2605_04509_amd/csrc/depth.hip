@@ -33,13 +33,19 @@ constexpr int kSplitItems = kSplitTile / kSplitBlock;
 constexpr int kSplitTilesPerBlock = 4;  // histogram tiles per block (one cluster)
 
 // Histogram of bin = key >> 20 over the valid keys of each cluster's segment.
-// Block (x, k) covers tiles [x t, (x + 1) t) of cluster k's segment.
+// Block (x, k) covers tiles [x t, (x + 1) t) of cluster k's segment.  A
+// cluster's keys fall in few bins, so the lanes of one atomic instruction
+// often share a bin: lane l counts into copy l & 3 of the histogram (copies
+// kSplitBins + 1 words apart, so a bin's copies lie in different banks),
+// which cuts those collisions fourfold.
+constexpr int kSplitCopies = 4;
 __global__ void __launch_bounds__(kSplitBlock) split_hist_kernel(const uint32_t *__restrict__ dkey, int64_t Mp,
                                                                   uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t h[kSplitBins];
+    __shared__ uint32_t h[kSplitCopies * (kSplitBins + 1)];
     const int k = blockIdx.y;
-    for (int b = threadIdx.x; b < kSplitBins; b += kSplitBlock) h[b] = 0u;
+    uint32_t *hc = h + (threadIdx.x & (kSplitCopies - 1)) * (kSplitBins + 1);
+    for (int b = threadIdx.x; b < kSplitCopies * (kSplitBins + 1); b += kSplitBlock) h[b] = 0u;
     __syncthreads();
     const int64_t tps = Mp / kSplitTile;
     const int64_t t0 = (int64_t)blockIdx.x * kSplitTilesPerBlock;
@@ -51,11 +57,15 @@ __global__ void __launch_bounds__(kSplitBlock) split_hist_kernel(const uint32_t 
         for (int it = 0; it < kSplitItems; ++it) v[it] = seg[t * kSplitTile + it * kSplitBlock + threadIdx.x];
 #pragma unroll
         for (int it = 0; it < kSplitItems; ++it)
-            if (v[it] < 0x80000000u) atomicAdd(&h[v[it] >> kSplitShift], 1u);
+            if (v[it] < 0x80000000u) atomicAdd(&hc[v[it] >> kSplitShift], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kSplitBins; b += kSplitBlock)
-        if (h[b]) atomicAdd(&hist[(int64_t)k * kSplitBins + b], h[b]);
+    for (int b = threadIdx.x; b < kSplitBins; b += kSplitBlock) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kSplitCopies; ++q) c += h[q * (kSplitBins + 1) + b];
+        if (c) atomicAdd(&hist[(int64_t)k * kSplitBins + b], c);
+    }
 }
 
 // thr[k] = (largest bin boundary b with at most R keys in bins below b) << 20;

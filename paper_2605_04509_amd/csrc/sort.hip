@@ -38,8 +38,13 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
                                                                 uint32_t *hist, int64_t nb, int64_t seg)
 {
     const int64_t n = sort_count(n_cap, dn);
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    // four copies of the histogram, lane l counting into copy l & 3 (257
+    // words apart: a digit's copies lie in different banks), so that lanes of
+    // one atomic instruction collide four times less often on a digit that
+    // many keys share (the top digit of float depths takes few values)
+    __shared__ uint32_t h[4 * 257];
+    uint32_t *hc = h + (threadIdx.x & 3) * 257;
+    for (int b = threadIdx.x; b < 4 * 257; b += kSortBlock) h[b] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     // all of a thread's keys are loaded before the first is counted (a
@@ -55,10 +60,12 @@ __global__ void __launch_bounds__(kSortBlock) sort_hist_kernel(const K *__restri
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t idx = base + it * kSortBlock + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(uint32_t)(k[it] >> shift) & mask], 1u);
+        if (idx < n) atomicAdd(&hc[(uint32_t)(k[it] >> shift) & mask], 1u);
     }
     __syncthreads();
-    if (threadIdx.x <= mask) hist[hist_index(threadIdx.x, blockIdx.x, nb, seg, (int)mask + 1)] = h[threadIdx.x];
+    if (threadIdx.x <= mask)
+        hist[hist_index(threadIdx.x, blockIdx.x, nb, seg, (int)mask + 1)] =
+            h[threadIdx.x] + h[257 + threadIdx.x] + h[514 + threadIdx.x] + h[771 + threadIdx.x];
 }
 
 // Scatter of one 4096-key tile.  Wavefront w ranks the contiguous keys
