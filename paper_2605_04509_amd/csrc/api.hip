@@ -26,7 +26,7 @@ enum Slot {
     kRec, kDKey0, kDVal0, kDKey1, kDVal1, kMean2D, kCounts, kWaveMask, kOffsets, kScanTemp,
     kPairK0, kPairV0, kPairK1, kPairV1, kSortTemp, kRanges, kCams, kTables, kTotal, kImages, kBatchSlot,
     kWork, kAlive, kAliveBits, kState, kTaskAlive, kSaveT, kSaveEnd, kDRec, kDMean, kBatchTables, kBatchNeed,
-    kAliveSat, kItemBox, kNearK0, kNearV0, kNearK1, kNearV1, kSplit, kFarK0, kFarK1, kNumSlots
+    kAliveSat, kItemBox, kNearK0, kNearV0, kNearK1, kNearV1, kSplit, kFarK0, kFarK1, kAliveMask, kNumSlots
 };
 
 struct Buf {
@@ -521,6 +521,7 @@ BinParams bin_params(const Grid &d_, const DevTables &dt, const ViewTables &vt, 
     bp.alive_total = nullptr;
     bp.alive_sat = nullptr;
     bp.far_thr = nullptr;
+    bp.alive_mask = nullptr;
     return bp;
 }
 
@@ -959,7 +960,9 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
     };
     CHK(reset_state());
     uint32_t *alive_sat;
+    uint64_t *alive_mask;
     CHK(ws_get_t(ctx, kAliveSat, (size_t)vt.n_clusters * (d->TY + 1) * (d->TX + 1) + 1, &alive_sat));
+    CHK(ws_get_t(ctx, kAliveMask, (size_t)vt.n_clusters * 4, &alive_mask));
 
     BlendParams bp;
     bp.W = d->W;
@@ -1047,8 +1050,9 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
             ++ctx->stats.blend_launches;
             if (!last) {
                 HIPCHK(ctx, launch_alive_tables(tc_alive, vt.n_clusters, d->TX, d->TY, words, pr.cbits, alive_bits,
-                                                alive_sat, s));
+                                                alive_sat, alive_mask, s));
                 bin.alive_sat = alive_sat;   // later chunks skip items whose tiles are all saturated
+                bin.alive_mask = alive_tables_have_masks(d->TX, d->TY) ? alive_mask : nullptr;
                 tm.span(kStRanges, e1, tm.mark(s));
             }
             blend_ran = true;
@@ -1065,6 +1069,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
             single = true;
             CHK(reset_state());
             bin.alive_sat = nullptr;
+            bin.alive_mask = nullptr;
             if (bp.work) HIPCHK(ctx, launch_fill_u32((uint32_t *)bp.work, 0u, 8, s));
             ctx->stats.blend_launches = 0;
             blend_ran = false;

@@ -38,6 +38,26 @@ __device__ inline bool rect_alive(const BinParams &bp, int k, ushort4 b)
     return S[y1 * pitch + x1] - S[y0 * pitch + x1] - S[y1 * pitch + x0] + S[y0 * pitch + x0] != 0u;
 }
 
+// Tiles [lo, hi] (0 <= lo <= hi < 64) as a 64-bit mask.
+__device__ __forceinline__ uint64_t span64(int lo, int hi)
+{
+    return (hi >= 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
+}
+
+// Whether the tile rectangle b can hold an alive (tile, cluster k) list by
+// the cluster's masks of tile rows and tile columns with any alive list
+// (registers only; rect_alive then decides).  Always true without masks.
+__device__ inline bool box_may_live(const BinParams &bp, int k, ushort4 b)
+{
+    if (!bp.alive_mask) return true;
+    const uint64_t *m = bp.alive_mask + 4 * (int64_t)k;
+    const uint64_t rows = m[0], c0 = m[1], c1 = m[2];
+    const int x0 = b.x, x1 = b.y;
+    const uint64_t lo = x0 < 64 ? span64(x0, min(x1, 63)) : 0ull;
+    const uint64_t hi = x1 >= 64 ? span64(max(x0, 64) - 64, x1 - 64) : 0ull;
+    return (span64(b.z, b.w) & rows) != 0ull && ((lo & c0) | (hi & c1)) != 0ull;
+}
+
 // The x-range [xl, xr] (relative to the mean, padded) of the cutoff ellipse
 // E <= E_c of record r, E = a (dx + beta dy)^2 + g dy^2, over the rows dy in
 // [dlo, dhi]; false when no such row meets it.  For dy in an interval inside
@@ -267,11 +287,19 @@ __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *_
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
             obox = kFar ? fbox : bp.ibox[(int64_t)k * bp.M + i];
-            if (kEmit || !bp.alive_sat || rect_alive(bp, k, obox)) {
+            if (kEmit || !bp.alive_sat || (box_may_live(bp, k, obox) && rect_alive(bp, k, obox))) {
                 own = items_k[i];
                 U = item_units(obox);
             }
         }
+    }
+    // a counting run without units: nothing to count
+    if (!kEmit && __ballot(U > 0) == 0ull) {
+        if (lane == 0) {
+            wcnt[w] = 0u;
+            wmask[w] = 0ull;
+        }
+        return;
     }
     const uint32_t uincl = wave_incl_scan((uint32_t)U, lane);
     const uint32_t ubase = uincl - (uint32_t)U;
@@ -480,9 +508,13 @@ constexpr int kSatLdsMax = 12288;  // 48 KB
 __global__ void __launch_bounds__(kSatBlock) alive_tables_kernel(const uint32_t *__restrict__ tc_alive, int TX,
                                                                   int TY, int words, int cluster_bits,
                                                                   uint32_t *__restrict__ bits,
-                                                                  uint32_t *__restrict__ sat)
+                                                                  uint32_t *__restrict__ sat,
+                                                                  uint64_t *__restrict__ masks)
 {
     __shared__ uint32_t S[kSatLdsMax];
+    __shared__ unsigned long long s_mask[3];  // rows, columns 0..63, columns 64..127 with an alive list
+    if (threadIdx.x < 3) s_mask[threadIdx.x] = 0ull;
+    __syncthreads();
     const int k = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int pitch = TX + 1, n = (TY + 1) * pitch;
@@ -504,9 +536,12 @@ __global__ void __launch_bounds__(kSatBlock) alive_tables_kernel(const uint32_t 
             const uint32_t incl = wave_incl_scan(v, lane);
             if (tx < TX) row[tx + 1] = carry + incl;
             carry += (uint32_t)__popcll(b);
+            if (lane == 0 && b != 0ull && x0 < 128) atomicOr(&s_mask[1 + (x0 >> 6)], (unsigned long long)b);
         }
+        if (lane == 0 && carry != 0u && ty < 64) atomicOr(&s_mask[0], 1ull << ty);
     }
     __syncthreads();
+    if (masks && threadIdx.x < 4) masks[4 * (int64_t)k + threadIdx.x] = threadIdx.x < 3 ? s_mask[threadIdx.x] : 0ull;
     for (int x = threadIdx.x; x <= TX; x += kSatBlock) {
         uint32_t run = 0;
         for (int y = 1; y <= TY; ++y) {
@@ -612,8 +647,13 @@ hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, in
     return hipGetLastError();
 }
 
+bool alive_tables_have_masks(int TX, int TY)
+{
+    return (int64_t)(TY + 1) * (TX + 1) <= kSatLdsMax && TY <= 64 && TX <= 128;
+}
+
 hipError_t launch_alive_tables(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words, int cluster_bits,
-                               uint32_t *bits, uint32_t *sat, hipStream_t s)
+                               uint32_t *bits, uint32_t *sat, uint64_t *masks, hipStream_t s)
 {
     if (n_clusters == 0) return hipSuccess;
     if ((int64_t)(TY + 1) * (TX + 1) > kSatLdsMax) {
@@ -622,7 +662,7 @@ hipError_t launch_alive_tables(const uint32_t *tc_alive, int n_clusters, int TX,
         return launch_alive_sat(tc_alive, n_clusters, TX, TY, cluster_bits, sat, s);
     }
     hipLaunchKernelGGL(alive_tables_kernel, dim3((unsigned)n_clusters), dim3(kSatBlock), 0, s, tc_alive, TX, TY, words,
-                       cluster_bits, bits, sat);
+                       cluster_bits, bits, sat, alive_tables_have_masks(TX, TY) ? masks : nullptr);
     return hipGetLastError();
 }
 

@@ -254,6 +254,7 @@ struct BinParams {
     const uint32_t *alive_total;  // unsaturated subpixels (planned frames exit early at 0), or null
     const uint32_t *alive_sat;    // [K'][TY+1][TX+1] summed-area table of alive lists, or null (all alive)
     const uint32_t *far_thr;      // [K'] depth-key thresholds of the far chunk (split depth order), or null
+    const uint64_t *alive_mask;   // [K'][4] tile rows, columns 0..63, 64..127 with an alive list, or null
 };
 // Per wavefront of 64 items (K' * ceil(len / 64) of them): pair total wcnt
 // and mask of the items with pairs wmask.  far: the far chunk of a split
@@ -281,9 +282,12 @@ hipError_t launch_alive_sat(const uint32_t *tc_alive, int n_clusters, int TX, in
 hipError_t launch_alive_bits(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
                              int cluster_bits, uint32_t *bits, hipStream_t s);
 // Both: the alive bits and the summed-area table, in one launch where the
-// table fits in LDS.
+// table fits in LDS; then also, for grids of at most 64 tile rows and 128
+// tile columns (alive_tables_have_masks), per cluster the masks of tile rows
+// and tile columns holding an alive list (masks: [K'][4] u64).
+bool alive_tables_have_masks(int TX, int TY);
 hipError_t launch_alive_tables(const uint32_t *tc_alive, int n_clusters, int TX, int TY, int words,
-                               int cluster_bits, uint32_t *bits, uint32_t *sat, hipStream_t s);
+                               int cluster_bits, uint32_t *bits, uint32_t *sat, uint64_t *masks, hipStream_t s);
 hipError_t launch_tc_count(const uint16_t *V, const int32_t *view_cluster, int W, int H, int tw, int th,
                            int cluster_bits, uint32_t *counts, hipStream_t s);
 
