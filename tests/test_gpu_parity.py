@@ -255,6 +255,41 @@ def test_equal_depths_keep_index_order_across_depth_chunks(lib, tiny_setup):
     d.close()
 
 
+@pytest.mark.parametrize("case", ["one_mean", "mostly_behind"])
+def test_split_depth_order_edge_cases(lib, tiny_setup, case):
+    """The two ends of the split depth order, against one chunk from a full
+    sort.  one_mean: every Gaussian at the tiny scene's first mean (colours,
+    opacities and shapes kept), so each cluster's keys are all equal and fall
+    in one histogram bin holding more than the ranked chunks' ranks: the near
+    set is empty and every item lies in the last chunk, whose 64-bit sort must
+    keep equal depths in index order (checked against the oracle too).
+    mostly_behind: nine Gaussians in ten moved behind the cameras, so fewer
+    valid keys than ranked ranks: the last chunk is empty."""
+    lfr, ctx = lib
+    w, scene, cams, V, _ = tiny_setup
+    means = scene.means.copy()
+    if case == "one_mean":
+        means[:] = means[0]
+    else:
+        means[np.arange(len(means)) % 10 != 0, 2] = -50.0
+    sc = Scene(means, scene.log_scales, scene.quats, scene.opacities, scene.sh, scene.sh_degree)
+    ds = lfr.DeviceScene.from_numpy(sc)
+    d = _display(lfr, ctx, w.display)
+    for S in (1, 4):
+        whole = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=1 << 20)
+        assert ctx.stats()["chunks"] == 1
+        if case == "one_mean" and S == 4:
+            r = oracle.render_frame_ranged(sc, cams, w.display, V, S)
+            say(compare(whole, r, colour_bound(sc), label=f"{case} S={S}"))
+        for fc in (5, 64):
+            img = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=fc)
+            st = ctx.stats()
+            say(case, "S =", S, "first chunk", fc, "chunks", st["chunks"], "pairs", st["pairs"])
+            assert st["chunks"] > 1
+            np.testing.assert_array_equal(img, whole)
+    d.close()
+
+
 @pytest.mark.parametrize("S,first_chunk", [(1, 0), (4, 0), (4, 64), (8, 7)])
 def test_work_counts_agree_across_blend_orders(lib, tiny_setup, S, first_chunk):
     """The counting renders report the method's work on the binned lists: the
