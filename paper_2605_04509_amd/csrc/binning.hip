@@ -268,18 +268,21 @@ __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *_
     ushort4 obox = make_ushort4(0, 0, 0, 0);
     // a cluster without any list that still has unsaturated subpixels emits
     // nothing (the summed-area table's total)
+    // (the cluster's test joins the item's below, so that the item loads
+    // are issued without waiting for it)
     const bool cluster_alive =
         !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
-    if (in && cluster_alive && ((wm >> lane) & 1ull)) {
+    if (in && ((wm >> lane) & 1ull)) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
         const uint32_t dk = dkey_sorted[e], dv = kFar ? (uint32_t)rl : dval_sorted[e];
         // (far items sit at their index: the box is loaded with the key)
         ushort4 fbox = make_ushort4(0, 0, 0, 0);
         if (kFar) fbox = bp.ibox[(int64_t)k * bp.M + rl];
         // (the index is tested too, though never all ones, so that its load
-        // is issued with the key's instead of after the key is known)
-        bool take = (dk != 0xFFFFFFFFu) & (dv != 0xFFFFFFFFu);
-        if (kFar) take = take & (dk >= bp.far_thr[k]);
+        // is issued with the key's instead of after the key is known; so is a
+        // far item's box, whose x0 <= x1 holds for every binned item)
+        bool take = cluster_alive & (dk != 0xFFFFFFFFu) & (dv != 0xFFFFFFFFu);
+        if (kFar) take = take & (dk >= bp.far_thr[k]) & (fbox.x <= fbox.y);
         if (take) {
             i = dv;
             dkey_own = dk;
@@ -374,7 +377,9 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
                                                            uint32_t *__restrict__ pair_vals)
 {
     __shared__ uint32_t s_cnt[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // (the wavefront index through readfirstlane: uniform, so the run and
+    // cluster arithmetic and the per-cluster loads are scalar)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // (run counts fit 32 bits: K' M < 2^32 items)
     const uint32_t nwk = (uint32_t)((len + 63) >> 6), nw = nwk * (uint32_t)bp.n_clusters;
     // every subpixel saturated (chunks planned ahead of time): no pairs
