@@ -44,18 +44,43 @@ __device__ __forceinline__ uint64_t span64(int lo, int hi)
     return (hi >= 63 ? ~0ull : ((2ull << hi) - 1ull)) & (~0ull << lo);
 }
 
-// Whether the tile rectangle b can hold an alive (tile, cluster k) list by
-// the cluster's masks of tile rows and tile columns with any alive list
-// (registers only; rect_alive then decides).  Always true without masks.
-__device__ inline bool box_may_live(const BinParams &bp, int k, ushort4 b)
+// What key generation reads per cluster, kept in scalar registers while a
+// wavefront's runs stay in one cluster: whether any of its lists is still
+// alive (the summed-area table's total), the last chunk's depth threshold,
+// and the masks of tile rows and tile columns with an alive list (all ones
+// without masks).
+struct ClusterInfo {
+    bool alive;
+    uint32_t thr;
+    uint64_t rows, c0, c1;
+};
+
+template <bool kFar>
+__device__ inline ClusterInfo cluster_info(const BinParams &bp, int k)
 {
-    if (!bp.alive_mask) return true;
-    const uint64_t *m = bp.alive_mask + 4 * (int64_t)k;
-    const uint64_t rows = m[0], c0 = m[1], c1 = m[2];
+    ClusterInfo c;
+    c.alive = !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
+    c.thr = kFar ? bp.far_thr[k] : 0u;
+    c.rows = c.c0 = c.c1 = ~0ull;
+    if (bp.alive_mask) {
+        const uint64_t *m = bp.alive_mask + 4 * (int64_t)k;
+        c.rows = m[0];
+        c.c0 = m[1];
+        c.c1 = m[2];
+    }
+    return c;
+}
+
+// Whether the tile rectangle b (inside 64 x 128 tiles when the masks are
+// real) can hold an alive list by the cluster's row and column masks
+// (registers only; rect_alive then decides).
+__device__ inline bool box_may_live(const ClusterInfo &c, ushort4 b)
+{
+    if (c.rows == ~0ull && c.c0 == ~0ull && c.c1 == ~0ull) return true;
     const int x0 = b.x, x1 = b.y;
     const uint64_t lo = x0 < 64 ? span64(x0, min(x1, 63)) : 0ull;
     const uint64_t hi = x1 >= 64 ? span64(max(x0, 64) - 64, x1 - 64) : 0ull;
-    return (span64(b.z, b.w) & rows) != 0ull && ((lo & c0) | (hi & c1)) != 0ull;
+    return (span64(b.z, b.w) & c.rows) != 0ull && ((lo & c.c0) | (hi & c.c1)) != 0ull;
 }
 
 // The x-range [xl, xr] (relative to the mean, padded) of the cutoff ellipse
@@ -248,7 +273,7 @@ __device__ inline int wave_search(uint32_t key, uint32_t x)
 template <bool kEmit, bool kFar>
 __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *__restrict__ dkey_sorted,
                                           const uint32_t *__restrict__ dval_sorted, int64_t r0, int64_t len, int k,
-                                          int64_t wk, int64_t w, uint32_t *__restrict__ wcnt,
+                                          const ClusterInfo &ci, int64_t wk, int64_t w, uint32_t *__restrict__ wcnt,
                                           uint64_t *__restrict__ wmask, const uint32_t *__restrict__ woff,
                                           uint64_t n_pairs, void *__restrict__ pair_keys_v,
                                           uint32_t *__restrict__ pair_vals, uint32_t *s_cnt)
@@ -264,14 +289,13 @@ __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *_
     const GaussRec *items_k = bp.items + (int64_t)k * bp.M;
     uint32_t i = 0, dkey_own = 0;
     int U = 0;
-    GaussRec own = {};  // this lane's item record and union tile box (when it has units)
+    // this lane's item record and union tile box (when it has units; only
+    // such lanes' are ever read, by the unit lanes' exchanges, so the record
+    // is not cleared: clearing it would wait for the previous run's loads)
+    GaussRec own;
     ushort4 obox = make_ushort4(0, 0, 0, 0);
     // a cluster without any list that still has unsaturated subpixels emits
-    // nothing (the summed-area table's total)
-    // (the cluster's test joins the item's below, so that the item loads
-    // are issued without waiting for it)
-    const bool cluster_alive =
-        !bp.alive_sat || bp.alive_sat[((int64_t)k * (bp.TY + 1) + bp.TY) * (bp.TX + 1) + bp.TX] != 0u;
+    // nothing (ci.alive: the summed-area table's total)
     if (in && ((wm >> lane) & 1ull)) {
         const int64_t e = (int64_t)k * bp.Mp + r0 + rl;
         const uint32_t dk = dkey_sorted[e], dv = kFar ? (uint32_t)rl : dval_sorted[e];
@@ -281,8 +305,8 @@ __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *_
         // (the index is tested too, though never all ones, so that its load
         // is issued with the key's instead of after the key is known; so is a
         // far item's box, whose x0 <= x1 holds for every binned item)
-        bool take = cluster_alive & (dk != 0xFFFFFFFFu) & (dv != 0xFFFFFFFFu);
-        if (kFar) take = take & (dk >= bp.far_thr[k]) & (fbox.x <= fbox.y);
+        bool take = ci.alive & (dk != 0xFFFFFFFFu) & (dv != 0xFFFFFFFFu);
+        if (kFar) take = take & (dk >= ci.thr) & (fbox.x <= fbox.y);
         if (take) {
             i = dv;
             dkey_own = dk;
@@ -290,7 +314,7 @@ __device__ __forceinline__ void chunk_run(const BinParams &bp, const uint32_t *_
             // pass tests the 8-byte union box before it reads the record
             // (the emitting pass only sees items with pairs)
             obox = kFar ? fbox : bp.ibox[(int64_t)k * bp.M + i];
-            if (kEmit || !bp.alive_sat || (box_may_live(bp, k, obox) && rect_alive(bp, k, obox))) {
+            if (kEmit || !bp.alive_sat || (box_may_live(ci, obox) && rect_alive(bp, k, obox))) {
                 own = items_k[i];
                 U = item_units(obox);
             }
@@ -384,6 +408,8 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
     const uint32_t nwk = (uint32_t)((len + 63) >> 6), nw = nwk * (uint32_t)bp.n_clusters;
     // every subpixel saturated (chunks planned ahead of time): no pairs
     const bool done = bp.alive_total && *bp.alive_total == 0u;
+    uint32_t kc = 0xFFFFFFFFu;  // the cluster whose values ci holds
+    ClusterInfo ci = {};
     for (uint32_t w = blockIdx.x * 4u + (uint32_t)wave; w < nw; w += gridDim.x * 4u) {
         const uint32_t k = w / nwk;
         if (done) {
@@ -393,8 +419,12 @@ __global__ void __launch_bounds__(256) chunk_tiles_kernel(BinParams bp, const ui
             }
             continue;
         }
-        chunk_run<kEmit, kFar>(bp, dkey_sorted, dval_sorted, r0, len, (int)k, (int64_t)(w - k * nwk), (int64_t)w,
-                               wcnt, wmask, woff, n_pairs, pair_keys_v, pair_vals, s_cnt[wave]);
+        if (k != kc) {
+            kc = k;
+            ci = cluster_info<kFar>(bp, (int)k);
+        }
+        chunk_run<kEmit, kFar>(bp, dkey_sorted, dval_sorted, r0, len, (int)k, ci, (int64_t)(w - k * nwk),
+                               (int64_t)w, wcnt, wmask, woff, n_pairs, pair_keys_v, pair_vals, s_cnt[wave]);
     }
 }
 
