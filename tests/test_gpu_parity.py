@@ -495,6 +495,36 @@ def test_display_workload_sampled(lib, S):
     d.close()
 
 
+def test_display_workload_tilings_and_chunks_agree(lib):
+    """The display workload in several depth chunks (the split depth order,
+    the alive tables between chunks) on three tilings that take different
+    code paths: 8x8 tiles (135 tile rows, a 136 x 241 summed-area table:
+    no row/column masks, the table built outside LDS), 32x32 and 32x64 (masks
+    and the LDS table).  Coverage is conservative, so every rendering must be
+    bit-identical, and equal to one chunk from a single full depth sort."""
+    lfr, ctx = lib
+    w = get_workload("display")
+    scene = w.make_scene()
+    cams = pack_cameras(w.cameras())
+    ds = lfr.DeviceScene.from_numpy(scene)
+    ref = None
+    for tile in ((32, 32), (8, 8), (32, 64)):
+        d = _display(lfr, ctx, w.display.with_tile(*tile))
+        for S, fc in ((4, 2048), (4, 1 << 20), (1, 4096)):
+            img = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=fc)
+            st = ctx.stats()
+            say("display tiling", tile, "S =", S, "first chunk", fc, "chunks", st["chunks"], "pairs", st["pairs"])
+            if fc != 1 << 20:
+                assert st["chunks"] > 1
+            if ref is None:
+                ref = {}
+            if S not in ref:
+                ref[S] = img
+            else:
+                np.testing.assert_array_equal(img, ref[S])
+        d.close()
+
+
 # the tile shapes the benchmark's autotuner chooses among
 BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64))
 
