@@ -1,5 +1,10 @@
-// Device-wide exclusive scan of uint32 values (three phases: per-tile sums,
-// a single-block scan of the tile sums, per-tile downsweep).  Sums are
+// Device-wide exclusive scan of uint32 values.  Tiles of 4096 values; each
+// downsweep block scans its tile with 16 consecutive values per thread and
+// adds the sum of all earlier tiles.  That sum comes from a per-tile
+// reduction launched first: up to 2048 tiles each downsweep block adds up
+// the earlier tiles' sums itself (two launches), beyond that a single-block
+// scan of the tile sums runs in between (three launches).  Up to 16384
+// values one 1024-thread block does everything in one launch.  Sums are
 // carried in 64 bits; the 64-bit grand total is written for the host, which
 // rejects totals that do not fit the 32-bit offsets.
 #include "lfr_internal.h"
@@ -9,8 +14,14 @@ namespace lfr {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kScanBigBlock = 1024;
+constexpr int kScanSingle = kScanBigBlock * kScanItems;     // values of a one-launch scan
+constexpr int kScanFoldLoads = 8;
+constexpr int kScanFoldTiles = kScanBlock * kScanFoldLoads;  // tiles a downsweep block sums itself
 
-// Inclusive scan of one value per thread across a 256-thread block.
+// Inclusive scan of one value per thread across a block of B threads; the
+// block's total goes to *block_total.
+template <int B>
 __device__ inline uint64_t block_inclusive_scan(uint64_t v, uint64_t *wave_sums, uint64_t *block_total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -23,7 +34,7 @@ __device__ inline uint64_t block_inclusive_scan(uint64_t v, uint64_t *wave_sums,
     __syncthreads();
     uint64_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kScanBlock / 64; ++w) {
+    for (int w = 0; w < B / 64; ++w) {
         const uint64_t s = wave_sums[w];
         if (w < wave) before += s;
         total += s;
@@ -52,10 +63,12 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t 
         s += idx < n ? v[it] : 0u;
     }
     uint64_t total;
-    block_inclusive_scan(s, ws, &total);
+    block_inclusive_scan<kScanBlock>(s, ws, &total);
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
+// Exclusive scan of the tile sums in place (one block), for more tiles than
+// a downsweep block adds up itself.
 __global__ void __launch_bounds__(kScanBlock) scan_partials_kernel(uint64_t *partial, int64_t nb, uint64_t *total_out)
 {
     __shared__ uint64_t ws[kScanBlock / 64];
@@ -64,46 +77,48 @@ __global__ void __launch_bounds__(kScanBlock) scan_partials_kernel(uint64_t *par
         const int64_t idx = base + threadIdx.x;
         const uint64_t v = idx < nb ? partial[idx] : 0;
         uint64_t tot;
-        const uint64_t inc = block_inclusive_scan(v, ws, &tot);
+        const uint64_t inc = block_inclusive_scan<kScanBlock>(v, ws, &tot);
         if (idx < nb) partial[idx] = carry + inc - v;
         carry += tot;
     }
     if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
-__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t *in, uint32_t *out, int64_t n,
-                                                                const uint64_t *partial)
+// Downsweep of tile blockIdx.x (B x 16 values, thread t on values 16t ..
+// 16t + 15 of the tile, read and written as 16-byte vectors when in and out
+// are 16-byte aligned).  The tile's offset is partial[blockIdx.x] when the
+// tile sums were scanned (kFold false); otherwise (kFold, at most
+// kScanFoldTiles tiles) this block adds up the sums partial[0 .. blockIdx.x)
+// of the earlier tiles, and the last tile writes the grand total.
+template <int B, bool kFold>
+__global__ void __launch_bounds__(B) scan_down_kernel(const uint32_t *in, uint32_t *out, int64_t n,
+                                                       const uint64_t *partial, uint64_t *total_out)
 {
-    __shared__ uint64_t ws[kScanBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint64_t carry = partial[blockIdx.x];
-    // items in striped order (it-major, then thread): the scan order is the
-    // index order because idx = base + it*256 + tid
-    for (int it = 0; it < kScanItems; ++it) {
-        const int64_t idx = base + it * kScanBlock + threadIdx.x;
-        const uint64_t v = idx < n ? in[idx] : 0;
-        uint64_t tot;
-        const uint64_t inc = block_inclusive_scan(v, ws, &tot);
-        if (idx < n) out[idx] = (uint32_t)(carry + inc - v);
-        carry += tot;
+    __shared__ uint64_t ws[B / 64];
+    uint64_t carry;
+    if (kFold) {
+        // every load issued before any is summed (index 0 stands in past the end)
+        uint64_t p[kScanFoldLoads];
+#pragma unroll
+        for (int q = 0; q < kScanFoldLoads; ++q) {
+            const int j = q * B + (int)threadIdx.x;
+            p[q] = partial[j < (int)blockIdx.x ? j : 0];
+        }
+        uint64_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kScanFoldLoads; ++q) c += q * B + (int)threadIdx.x < (int)blockIdx.x ? p[q] : 0ull;
+        block_inclusive_scan<B>(c, ws, &carry);
+    } else {
+        carry = partial[blockIdx.x];
     }
-}
-
-// The same downsweep with each thread on 16 consecutive items (read and
-// written as four 16-byte vectors): one block scan per tile instead of
-// sixteen.  For 16-byte aligned in / out.
-__global__ void __launch_bounds__(kScanBlock) scan_down_blocked_kernel(const uint32_t *in, uint32_t *out, int64_t n,
-                                                                        const uint64_t *partial)
-{
-    __shared__ uint64_t ws[kScanBlock / 64];
-    const int64_t t0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    const bool full = t0 + kScanItems <= n;
+    const int64_t t0 = (int64_t)blockIdx.x * (B * kScanItems) + (int64_t)threadIdx.x * kScanItems;
+    const bool vec = t0 + kScanItems <= n && ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0);
     uint32_t v[kScanItems];
-    if (full) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(in + t0);
+    if (vec) {
+        const uint4 *pv = reinterpret_cast<const uint4 *>(in + t0);
 #pragma unroll
         for (int j = 0; j < kScanItems / 4; ++j) {
-            const uint4 q = p[j];
+            const uint4 q = pv[j];
             v[4 * j] = q.x;
             v[4 * j + 1] = q.y;
             v[4 * j + 2] = q.z;
@@ -111,21 +126,23 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_blocked_kernel(const uin
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) v[k] = t0 + k < n ? in[t0 + k] : 0u;
+        for (int k = 0; k < kScanItems; ++k) v[k] = in[t0 + k < n ? t0 + k : 0];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = t0 + k < n ? v[k] : 0u;
     }
     uint64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) sum += v[k];
     uint64_t tot;
-    const uint64_t inc = block_inclusive_scan(sum, ws, &tot);
-    uint64_t run = partial[blockIdx.x] + inc - sum;
+    const uint64_t inc = block_inclusive_scan<B>(sum, ws, &tot);
+    uint64_t run = carry + inc - sum;
     uint32_t o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         o[k] = (uint32_t)run;
         run += v[k];
     }
-    if (full) {
+    if (vec) {
         uint4 *q = reinterpret_cast<uint4 *>(out + t0);
 #pragma unroll
         for (int j = 0; j < kScanItems / 4; ++j) q[j] = make_uint4(o[4 * j], o[4 * j + 1], o[4 * j + 2], o[4 * j + 3]);
@@ -134,6 +151,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_blocked_kernel(const uin
         for (int k = 0; k < kScanItems; ++k)
             if (t0 + k < n) out[t0 + k] = o[k];
     }
+    if (kFold && total_out && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total_out = carry + tot;
 }
 
 size_t scan_temp_bytes(int64_t n)
@@ -145,20 +163,28 @@ size_t scan_temp_bytes(int64_t n)
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, void *temp, uint64_t *total,
                                  hipStream_t s)
 {
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     uint64_t *partial = (uint64_t *)temp;
     if (n == 0) {
+        // nothing to read: only the total (zero)
         if (total) hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, (int64_t)0, total);
         return hipGetLastError();
     }
+    if (n <= kScanSingle) {
+        // one block; with no earlier tile it reads no tile sum
+        hipLaunchKernelGGL((scan_down_kernel<kScanBigBlock, true>), dim3(1), dim3(kScanBigBlock), 0, s, in, out, n,
+                           (const uint64_t *)partial, total);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, partial);
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, nb, total);
-    if ((((uintptr_t)in | (uintptr_t)out) & 15u) == 0)
-        hipLaunchKernelGGL(scan_down_blocked_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
-                           (const uint64_t *)partial);
-    else
-        hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
-                           (const uint64_t *)partial);
+    if (nb <= kScanFoldTiles) {
+        hipLaunchKernelGGL((scan_down_kernel<kScanBlock, true>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out,
+                           n, (const uint64_t *)partial, total);
+    } else {
+        hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanBlock), 0, s, partial, nb, total);
+        hipLaunchKernelGGL((scan_down_kernel<kScanBlock, false>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out,
+                           n, (const uint64_t *)partial, (uint64_t *)nullptr);
+    }
     return hipGetLastError();
 }
 

@@ -93,9 +93,13 @@ def test_display_from_map_and_errors(lib):
 # device sort: bit-exact against a stable argsort
 # --------------------------------------------------------------------------
 
+# The digit-count scans run in one launch up to 16384 counts (64 sort tiles of
+# 256 digits), in two above that: 262144 keys sit at the boundary, 262145
+# and the larger cases past it.
 @pytest.mark.parametrize("n,bits,wide", [(1, 32, False), (1000, 32, False), (123457, 19, False),
                                          (300001, 13, False), (200003, 40, True), (65536, 64, True),
-                                         (4097, 7, False)])
+                                         (4097, 7, False), (262144, 32, False), (262145, 32, False),
+                                         (2000003, 24, False), (300001, 64, True)])
 def test_radix_sort_stable(lib, n, bits, wide):
     lfr, ctx = lib
     say("sort", n, bits, wide)
@@ -113,6 +117,32 @@ def test_radix_sort_stable(lib, n, bits, wide):
     order = np.argsort(keys, kind="stable")
     np.testing.assert_array_equal(kd.cpu().numpy().view(keys.dtype), keys[order])
     np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_radix_sort_stable_large(lib):
+    """More than 2048 scan tiles of digit counts (32770 sort tiles x 256
+    digits): the scans take their three-launch form.  Checked on the device
+    by the properties that define a stable sort: keys non-decreasing, each
+    output key the input key at its output index, indices a permutation,
+    increasing within runs of equal keys."""
+    lfr, ctx = lib
+    n = 32770 * 4096 - 3
+    say("sort large", n)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    keys = torch.randint(0, 1 << 20, (n,), device="cuda", dtype=torch.int32, generator=g)
+    keys[: n // 4] = 12345                            # a long run of ties
+    kd = keys.clone()
+    vd = torch.arange(n, device="cuda", dtype=torch.int32)
+    lfr.sort_pairs(ctx, kd, vd, 0, 32)
+    torch.cuda.synchronize()
+    idx = vd.long()
+    assert bool((kd[1:] >= kd[:-1]).all())
+    assert bool((keys[idx] == kd).all())
+    assert bool((torch.bincount(idx, minlength=n) == 1).all())
+    tie = kd[1:] == kd[:-1]
+    assert bool((vd[1:][tie] > vd[:-1][tie]).all())
+    del keys, kd, vd, idx, tie
+    torch.cuda.empty_cache()
 
 
 # --------------------------------------------------------------------------
