@@ -57,7 +57,7 @@ struct SavedForward {
     const uint2 *ranges = nullptr;
     const uint32_t *vals = nullptr;
     const Task *tasks = nullptr;
-    int n_tasks = 0;
+    int n_tasks = 0, xcd_shift = 4;
     const float *save_T = nullptr;
     const uint32_t *save_end = nullptr;
 };
@@ -669,6 +669,24 @@ lfr_status order_tasks(lfr_context *ctx, const lfr_display *d, Task *d_tasks, in
     return LFR_OK;
 }
 
+// Size of the blend's XCD task groups (log2): about the work items of one
+// kTaskBlock x kTaskBlock block of tiles of one cluster (16 times the mean
+// items per (tile, cluster) list, to the nearest power of two, 16 .. 512),
+// so that the items reading the records of neighbouring tiles run on one
+// XCD.  Measured on the outdoor frame (8 items per list: flat from 16 to
+// 128) and the paper's display shapes (about 25 per list: the blend 10-17%
+// faster at 512 than at 16).
+int xcd_group_shift(const std::vector<Task> &h)
+{
+    if (h.empty()) return 4;
+    int64_t lists = 1;
+    for (size_t e = 1; e < h.size(); ++e)
+        lists += (h[e].tile != h[e - 1].tile || h[e].cluster != h[e - 1].cluster) ? 1 : 0;
+    const double g = (double)(kTaskBlock * kTaskBlock) * (double)h.size() / (double)lists;
+    const int sh = (int)std::lround(std::log2(std::max(g, 1.0)));
+    return std::min(9, std::max(4, sh));
+}
+
 // Blend work items and per-(tile, cluster) subpixel counts for cluster
 // size S, built once per display.
 lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const ViewTables &vt, TaskSet **out)
@@ -728,6 +746,7 @@ lfr_status get_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, const 
     ts.n = (int)n;
     std::vector<Task> h;
     CHK(order_tasks(ctx, d, ts.d_tasks, ts.n, &h));
+    ts.xcd_shift = xcd_group_shift(h);
     guard.keep = true;
     auto ins = d->tasks.emplace(key, ts);
     *out = &ins.first->second;
@@ -776,6 +795,7 @@ lfr_status get_group_layout(lfr_context *ctx, lfr_display *d, int S, bool cull, 
     TaskSet ts;
     ts.cluster_bits = cbg;
     ts.n = F * base->n;
+    ts.xcd_shift = base->xcd_shift;
     struct Guard {
         std::vector<void *> p;
         bool keep = false;
@@ -1042,7 +1062,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
             bp.last = last ? 1 : 0;
             const size_t e0 = tm.mark(s);
             if (remap)
-                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, s));
+                HIPCHK(ctx, launch_blend_remap(bp, ts->d_tasks, ts->n, ts->xcd_shift, s));
             else
                 HIPCHK(ctx, launch_blend_rowmajor(bp, s));
             const size_t e1 = tm.mark(s);
@@ -1107,6 +1127,7 @@ lfr_status render_group(lfr_context *ctx, const lfr_display *display, const lfr_
         sv.vals = saved_chunk.vals;
         sv.tasks = ts->d_tasks;
         sv.n_tasks = ts->n;
+        sv.xcd_shift = ts->xcd_shift;
         sv.save_T = bp.save_T;
         sv.save_end = bp.save_end;
         sv.valid = true;
@@ -1476,7 +1497,7 @@ lfr_status lfr_render_backward(lfr_context *ctx, uint64_t saved_forward, const l
     bp.d_rec = d_rec;
     bp.d_mean2d = d_mean;
     const size_t e0 = tm.mark(s);
-    if (M > 0 && sv.ranges) HIPCHK(ctx, launch_blend_backward(bp, sv.tasks, sv.n_tasks, s));
+    if (M > 0 && sv.ranges) HIPCHK(ctx, launch_blend_backward(bp, sv.tasks, sv.n_tasks, sv.xcd_shift, s));
     const size_t e1 = tm.mark(s);
     tm.span(kStBwdBlend, e0, e1);
     SceneGrads sg{grads->means, grads->log_scales, grads->quats, grads->opacities, grads->sh};

@@ -57,21 +57,21 @@ __device__ __forceinline__ float2 sanitize_mean(float2 m)
 }
 
 // Block index -> task index.  Blocks are dealt to the 8 XCDs round-robin;
-// XCD x runs task groups x, x + 8, x + 16, ... (groups of kXcdGroup
-// consecutive tasks) in order.  The tasks of one (tile, cluster) list are
-// consecutive, so they mostly share one XCD and its L2, while every XCD
-// sweeps the whole panel: the work per tile varies strongly across the
-// panel, and contiguous eighths of it would leave some XCDs idle early.
-// The grid is rounded up to whole rounds of 8 groups.
-constexpr int kXcdGroup = 16;
-__device__ __forceinline__ int xcd_task(int b)
+// XCD x runs task groups x, x + 8, x + 16, ... (groups of 2^sh consecutive
+// tasks) in order.  Tasks are ordered cluster by cluster over blocks of
+// neighbouring tiles, so a group sized to about one such block keeps the
+// tasks that read the same Gaussians' records on one XCD and its L2, while
+// every XCD sweeps the whole panel: the work per tile varies strongly
+// across the panel, and contiguous eighths of it would leave some XCDs idle
+// early.  The grid is rounded up to whole rounds of 8 groups.
+__device__ __forceinline__ int xcd_task(int b, int sh)
 {
     const int x = b & 7, l = b >> 3;
-    return ((l / kXcdGroup) * 8 + x) * kXcdGroup + (l % kXcdGroup);
+    return ((((l >> sh) << 3) + x) << sh) + (l & ((1 << sh) - 1));
 }
-static unsigned xcd_grid(int n_tasks)
+static unsigned xcd_grid(int n_tasks, int sh)
 {
-    const int r = 8 * kXcdGroup;
+    const int r = 8 << sh;
     return (unsigned)((n_tasks + r - 1) / r * r);
 }
 
@@ -113,7 +113,7 @@ __device__ __forceinline__ void load_state(const BlendParams &bp, uint32_t at, f
 // the fold) and the end of its blended list for the backward.
 template <bool kCount, bool kSave>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) blend_remap_kernel(BlendParams bp, const Task *__restrict__ tasks,
-                                                          int n_tasks)
+                                                          int n_tasks, int xcd_shift)
 {
     __shared__ float4 s_a[kWave];
     __shared__ float s_c[kWave * 4];
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
     __shared__ float4 s_box[kMaxWaveViews];         // per view run: unfinished lanes' x0, x1, y0, y1
     __shared__ uint32_t s_pos[kSave || kCount ? kWave : 1];  // list position of each staged entry
 
-    const int ti = xcd_task(blockIdx.x);
+    const int ti = xcd_task(blockIdx.x, xcd_shift);
     if (ti >= n_tasks) return;
     // the item and its alive flag are loaded together (the test reads both;
     // an item always has at least one lane)
@@ -590,14 +590,14 @@ __device__ __forceinline__ int rev4(int l)
 }
 
 __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const Task *__restrict__ tasks,
-                                                             int n_tasks)
+                                                             int n_tasks, int xcd_shift)
 {
     __shared__ float4 s_a[kWave];
     __shared__ float s_c[kWave * 4];
     __shared__ float2 s_mu[kMaxWaveViews][kWave];
     __shared__ uint32_t s_i[kWave];
 
-    const int ti = xcd_task(blockIdx.x);
+    const int ti = xcd_task(blockIdx.x, xcd_shift);
     if (ti >= n_tasks) return;
     const Task tk = tasks[ti];
     const int lane = threadIdx.x;
@@ -705,18 +705,19 @@ __global__ void __launch_bounds__(64) blend_backward_kernel(BwdParams bp, const 
     }
 }
 
-hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
+hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks, int xcd_shift, hipStream_t s)
 {
     if (n_tasks == 0) return hipSuccess;
-    const dim3 grid(xcd_grid(n_tasks)), block(kWave);
+    if (xcd_shift < 0 || xcd_shift > 12) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(n_tasks, xcd_shift)), block(kWave);
     if (bp.work && bp.save_T)
-        hipLaunchKernelGGL((blend_remap_kernel<true, true>), grid, block, 0, s, bp, tasks, n_tasks);
+        hipLaunchKernelGGL((blend_remap_kernel<true, true>), grid, block, 0, s, bp, tasks, n_tasks, xcd_shift);
     else if (bp.work)
-        hipLaunchKernelGGL((blend_remap_kernel<true, false>), grid, block, 0, s, bp, tasks, n_tasks);
+        hipLaunchKernelGGL((blend_remap_kernel<true, false>), grid, block, 0, s, bp, tasks, n_tasks, xcd_shift);
     else if (bp.save_T)
-        hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks);
+        hipLaunchKernelGGL((blend_remap_kernel<false, true>), grid, block, 0, s, bp, tasks, n_tasks, xcd_shift);
     else
-        hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks);
+        hipLaunchKernelGGL((blend_remap_kernel<false, false>), grid, block, 0, s, bp, tasks, n_tasks, xcd_shift);
     return hipGetLastError();
 }
 
@@ -734,10 +735,12 @@ hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, hipStream_t s)
+hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, int xcd_shift, hipStream_t s)
 {
     if (n_tasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(blend_backward_kernel, dim3(xcd_grid(n_tasks)), dim3(kWave), 0, s, bp, tasks, n_tasks);
+    if (xcd_shift < 0 || xcd_shift > 12) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(blend_backward_kernel, dim3(xcd_grid(n_tasks, xcd_shift)), dim3(kWave), 0, s, bp, tasks,
+                       n_tasks, xcd_shift);
     return hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ struct TaskSet {
     int32_t *d_view_cluster = nullptr;    // [N]
     uint32_t *d_tc_count = nullptr;       // [T << cluster_bits]
     int cluster_bits = 0;
+    int xcd_shift = 4;                    // log2 of the blend's XCD task group (xcd_task)
 };
 
 // Stage timer: HIP events recorded on the working stream, summed per stage
@@ -319,7 +320,7 @@ struct BlendParams {
     float *save_T;                // per subpixel: final transmittance
     uint32_t *save_end;           // per subpixel: 1 + position of its last blended pair (0: none)
 };
-hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks,
+hipError_t launch_blend_remap(const BlendParams &bp, const Task *tasks, int n_tasks, int xcd_shift,
                               hipStream_t s);
 
 hipError_t launch_blend_rowmajor(const BlendParams &bp, hipStream_t s);
@@ -344,7 +345,7 @@ struct BwdParams {
     GradRec *d_rec;               // [K'][M], zeroed by the caller
     float2 *d_mean2d;             // [N'][M], zeroed by the caller
 };
-hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, hipStream_t s);
+hipError_t launch_blend_backward(const BwdParams &bp, const Task *tasks, int n_tasks, int xcd_shift, hipStream_t s);
 
 // Projection backward: per Gaussian, the record gradients of every cluster
 // and the mean gradients of every view -> parameter gradients.
