@@ -92,19 +92,34 @@ __device__ inline bool box_may_live(const ClusterInfo &c, ushort4 b)
 // left edge is its mirror image.  So the extremes over the band are at dy*
 // clamped into it.  E_c is the record's cutoff widened by 0.1% and 1e-3, and
 // the range by 1e-4 relative and 0.02 px: margins far above the float32
-// error of this evaluation and of the blend's.
-__device__ inline bool ellipse_xrange(const GaussRec &r, float dlo, float dhi, float &xl, float &xr)
+// error of this evaluation (hardware reciprocals and square roots, about
+// one ulp each) and of the blend's.
+//
+// What does not depend on the row band is computed once per record
+// (ellipse_of): E_c, 1/a, 1/g, the half height sqrt(E_c / g) and dy*.
+struct Ellipse {
+    float beta, g, ec, ia, hy, ds;
+};
+__device__ inline Ellipse ellipse_of(const GaussRec &r)
 {
-    const float ra = r.a.x, rbeta = r.a.y, rg = r.a.z;
-    const float Ec = r.c.w * 1.001f + 1e-3f;
-    const float hy = sqrtf(Ec / rg);
-    const float lo = fmaxf(dlo, -hy), hi = fminf(dhi, hy);
+    Ellipse e;
+    e.beta = r.a.y;
+    e.g = r.a.z;
+    e.ec = r.c.w * 1.001f + 1e-3f;
+    e.ia = __builtin_amdgcn_rcpf(r.a.x);
+    const float ig = __builtin_amdgcn_rcpf(r.a.z);
+    e.hy = __builtin_amdgcn_sqrtf(e.ec * ig);
+    const float S = e.ia + (e.beta * e.beta) * ig;
+    e.ds = -e.beta * __builtin_amdgcn_sqrtf(e.ec * __builtin_amdgcn_rcpf(S)) * ig;
+    return e;
+}
+__device__ inline bool ellipse_xrange(const Ellipse &e, float dlo, float dhi, float &xl, float &xr)
+{
+    const float lo = fmaxf(dlo, -e.hy), hi = fminf(dhi, e.hy);
     if (!(lo <= hi)) return false;
-    const float S = 1.0f / ra + rbeta * rbeta / rg;
-    const float ds = -rbeta * sqrtf(Ec / S) / rg;
-    const float t1 = fminf(fmaxf(ds, lo), hi), t2 = fminf(fmaxf(ds, -hi), -lo);
-    xr = -rbeta * t1 + sqrtf(fmaxf(Ec - rg * t1 * t1, 0.0f) / ra);
-    xl = rbeta * t2 - sqrtf(fmaxf(Ec - rg * t2 * t2, 0.0f) / ra);
+    const float t1 = fminf(fmaxf(e.ds, lo), hi), t2 = fminf(fmaxf(e.ds, -hi), -lo);
+    xr = -e.beta * t1 + __builtin_amdgcn_sqrtf(fmaxf(e.ec - e.g * t1 * t1, 0.0f) * e.ia);
+    xl = e.beta * t2 - __builtin_amdgcn_sqrtf(fmaxf(e.ec - e.g * t2 * t2, 0.0f) * e.ia);
     const float pad = 1e-4f * fmaxf(fabsf(xr), fabsf(xl)) + 0.02f;
     xl -= pad;
     xr += pad;
@@ -123,11 +138,11 @@ __device__ inline bool centre_cols(float xa, float xb, int W, int &c0, int &c1)
 }
 
 // Pixel columns [c0, c1] whose centres in pixel rows [y0, y1] can lie in the
-// cutoff ellipse of record r at mean m.
-__device__ inline bool row_span(const GaussRec &r, float2 m, int y0, int y1, int W, int &c0, int &c1)
+// cutoff ellipse e at mean m.
+__device__ inline bool row_span(const Ellipse &e, float2 m, int y0, int y1, int W, int &c0, int &c1)
 {
     float xl, xr;
-    if (!ellipse_xrange(r, (float)y0 + 0.5f - m.y, (float)y1 + 0.5f - m.y, xl, xr)) return false;
+    if (!ellipse_xrange(e, (float)y0 + 0.5f - m.y, (float)y1 + 0.5f - m.y, xl, xr)) return false;
     return centre_cols(m.x + xl, m.x + xr, W, c0, c1);
 }
 
@@ -136,10 +151,10 @@ __device__ inline bool row_span(const GaussRec &r, float2 m, int y0, int y1, int
 // over its own rows dy in [y0 + 0.5 - m.y, y1 + 0.5 - m.y], a sub-band of
 // [y0 + 0.5 - hi.y, y1 + 0.5 - lo.y]; so [lo.x + xl, hi.x + xr] over that
 // band holds all of them.
-__device__ inline bool hull_span(const GaussRec &r, float2 lo, float2 hi, int y0, int y1, int W, int &c0, int &c1)
+__device__ inline bool hull_span(const Ellipse &e, float2 lo, float2 hi, int y0, int y1, int W, int &c0, int &c1)
 {
     float xl, xr;
-    if (!ellipse_xrange(r, (float)y0 + 0.5f - hi.y, (float)y1 + 0.5f - lo.y, xl, xr)) return false;
+    if (!ellipse_xrange(e, (float)y0 + 0.5f - hi.y, (float)y1 + 0.5f - lo.y, xl, xr)) return false;
     return centre_cols(lo.x + xl, hi.x + xr, W, c0, c1);
 }
 
@@ -174,14 +189,15 @@ __device__ inline uint32_t unit_mask(const BinParams &bp, int k, uint32_t i, con
     uint32_t m = 0;
     const int y0 = ty * bp.th, y1 = min(y0 + bp.th, bp.H) - 1;
     const int v0 = bp.cv_off[k], nvk = bp.cv_off[k + 1] - v0;
+    const Ellipse el = ellipse_of(r);
     if (nvk > kItemViews) {
         int c0, c1;
-        if (hull_span(r, r.m[0], r.m[1], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
+        if (hull_span(el, r.m[0], r.m[1], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
     } else {
 #pragma unroll
         for (int v = 0; v < kItemViews; ++v) {
             int c0, c1;
-            if (v < nvk && row_span(r, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
+            if (v < nvk && row_span(el, r.m[v], y0, y1, bp.W, c0, c1)) m |= bits(c0 >> bp.tw_shift, c1 >> bp.tw_shift);
         }
     }
     const uint32_t *alive_k = bp.alive + (int64_t)k * bp.TY * bp.alive_words;
