@@ -218,16 +218,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) bl
     // Whether this lane's fetched Gaussian can reach any unfinished lane: the
     // region E <= E_cut lies in |dy| <= sqrt(E_cut / G'), |dx| <= sqrt(E_cut /
     // A') + |beta| |dy| (E = A'(dx + beta dy)^2 + G' dy^2), widened by 0.1%
-    // and 1e-3 px for rounding; outside it alpha < 0.9986 / 255 for every lane,
-    // so dropping the Gaussian changes nothing.
+    // and 1e-3 px for rounding (far above the one-ulp error of the hardware
+    // reciprocal and square root used here); outside it alpha < 0.9986 / 255
+    // for every lane, so dropping the Gaussian changes nothing.  (A cutoff of
+    // exactly 0 with a vanishing conic term gives NaN and drops the Gaussian:
+    // a cutoff below 0.01 never passes.)
     auto relevant = [&](uint32_t base) -> bool {
 #pragma unroll
         for (int q = 0; q < kMaxWaveViews; ++q) gm[q] = sanitize_mean(gm[q]);
         if (base + (uint32_t)lane >= range.y) return false;
         const float thr = gc.w;
         if (!(thr >= 0.0f)) return false;
-        const float hy = sqrtf(thr / ga.z) * 1.001f + 1e-3f;
-        const float hx = sqrtf(thr / ga.x) * 1.001f + fabsf(ga.y) * hy + 1e-3f;
+        const float hy = __builtin_amdgcn_sqrtf(thr * __builtin_amdgcn_rcpf(ga.z)) * 1.001f + 1e-3f;
+        const float hx = __builtin_amdgcn_sqrtf(thr * __builtin_amdgcn_rcpf(ga.x)) * 1.001f + fabsf(ga.y) * hy + 1e-3f;
         bool r = false;
 #pragma unroll
         for (int q = 0; q < kMaxWaveViews; ++q) {
