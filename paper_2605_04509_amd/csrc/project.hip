@@ -210,10 +210,12 @@ __device__ inline FullProj project_full(const DevCamera &c, const MeanProj &m, c
     // the float32 evaluation error here and that of the blend.
     constexpr float kInvHalfLog2e = (float)(1.0 / kHalfLog2e);
     const float Ar = f.conic[0] * kInvHalfLog2e, br = f.conic[1], Gr = f.conic[2] * kInvHalfLog2e;
-    // (hardware reciprocals: their error of about one ulp is far inside the margins)
+    // (hardware reciprocals and square roots: their error of about one ulp is
+    // far inside the margins)
     const float iG = __builtin_amdgcn_rcpf(Gr);
     const float S00 = __builtin_amdgcn_rcpf(Ar) + (br * br) * iG, S11 = iG;
-    f.ext = make_float2(__builtin_sqrtf(tau_o * S00) * 1.0001f + 0.02f, __builtin_sqrtf(tau_o * S11) * 1.0001f + 0.02f);
+    f.ext = make_float2(__builtin_amdgcn_sqrtf(tau_o * S00) * 1.0001f + 0.02f,
+                        __builtin_amdgcn_sqrtf(tau_o * S11) * 1.0001f + 0.02f);
     f.valid = isfinite(f.ext.x) && isfinite(f.ext.y);
     return f;
 }
