@@ -86,9 +86,10 @@ __device__ inline uint32_t tile_subpixel(const TileGeom &g, int W, int r)
 }
 
 // Psi for one tile: the tile's subpixels in row-major order (local rank r)
-// stably sorted by V.  Keys (V << 13) | r are unique (r < 3 * 64 * 32 <=
-// 8192), so a bitonic sort in LDS yields exactly the stable order.  One
-// 256-thread block per tile; LDS holds next_pow2(3 * tw * th) keys.
+// stably sorted by V.  Keys (V << 14) | r are unique (r < 3 * 64 * 64 <
+// 16384; V < 2^16, so keys stay below the all-ones padding), so a bitonic
+// sort in LDS yields exactly the stable order.  One 256-thread block per
+// tile; LDS holds next_pow2(3 * tw * th) keys (at most 16384, 64 KB).
 __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, int H, int tw, int th,
                                                     uint32_t *psi)
 {
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, in
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
     for (int r = threadIdx.x; r < n2; r += blockDim.x)
-        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 13) | (uint32_t)r) : 0xFFFFFFFFu;
+        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 14) | (uint32_t)r) : 0xFFFFFFFFu;
     __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, in
         }
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x)
-        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0x1FFFu));
+        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0x3FFFu));
 }
 
 hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_t *psi, hipStream_t s)

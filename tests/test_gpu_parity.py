@@ -348,7 +348,7 @@ def test_work_counts_agree_across_blend_orders(lib, tiny_setup, S, first_chunk):
     d.close()
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64)])
+@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64), (64, 64)])
 def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     lfr, ctx = lib
     w, scene, cams, V, ds = tiny_setup
@@ -529,8 +529,9 @@ def test_display_workload_tilings_and_chunks_agree(lib):
     """The display workload in several depth chunks (the split depth order,
     the alive tables between chunks) on three tilings that take different
     code paths: 8x8 tiles (135 tile rows, a 136 x 241 summed-area table:
-    no row/column masks, the table built outside LDS), 32x32 and 32x64 (masks
-    and the LDS table).  Coverage is conservative, so every rendering must be
+    no row/column masks, the table built outside LDS), 32x32, 32x64 and 64x64
+    (masks and the LDS table; 64x64 tiles of 12288 subpixels, the remap
+    table's largest sort).  Coverage is conservative, so every rendering must be
     bit-identical, and equal to one chunk from a single full depth sort."""
     lfr, ctx = lib
     w = get_workload("display")
@@ -538,7 +539,7 @@ def test_display_workload_tilings_and_chunks_agree(lib):
     cams = pack_cameras(w.cameras())
     ds = lfr.DeviceScene.from_numpy(scene)
     ref = None
-    for tile in ((32, 32), (8, 8), (32, 64)):
+    for tile in ((32, 32), (8, 8), (32, 64), (64, 64)):
         d = _display(lfr, ctx, w.display.with_tile(*tile))
         for S, fc in ((4, 2048), (4, 1 << 20), (1, 4096)):
             img = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=fc)
@@ -556,7 +557,7 @@ def test_display_workload_tilings_and_chunks_agree(lib):
 
 
 # the tile shapes the benchmark's autotuner chooses among
-BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64))
+BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64))
 
 
 @pytest.fixture(scope="module")
@@ -611,7 +612,7 @@ def test_paper_display_shapes(lib, outdoor, name, S):
     """The paper's two display shapes (71 views over 53 degrees at 3840x2160
     with reuse groups of 18; 63 views over 53 degrees at 1440x2560 with groups
     of 16, the last group padded) on the 3M-Gaussian scene, on the tile shapes
-    the benchmark picks (64x32 and 32x64, bit-identical): subpixels spread
+    the benchmark picks among (64x32, 32x64 and 64x64, bit-identical): subpixels spread
     over every view against the oracle, and the exact path's image against
     full-frame-then-interlace on the same display."""
     lfr, ctx = lib
@@ -623,7 +624,7 @@ def test_paper_display_shapes(lib, outdoor, name, S):
     assert len(np.unique(V)) == w.display.num_views
     ds = lfr.DeviceScene.from_numpy(scene)
     imgs = {}
-    for tile in ((64, 32), (32, 64)):
+    for tile in ((64, 32), (32, 64), (64, 64)):
         d = _display(lfr, ctx, w.display.with_tile(*tile))
         imgs[tile] = _render(lfr, ctx, d, ds, cams, cluster_size=S)
         say(" tile", tile, ctx.stats()["pairs"], "pairs")
@@ -634,6 +635,7 @@ def test_paper_display_shapes(lib, outdoor, name, S):
             np.testing.assert_array_equal(ff.cpu().numpy(), exact)
         d.close()
     np.testing.assert_array_equal(imgs[(64, 32)], imgs[(32, 64)])
+    np.testing.assert_array_equal(imgs[(64, 32)], imgs[(64, 64)])
     img = imgs[(64, 32)]
     samples, views = _sample_every_view(V, 2048, 3)
     assert w.display.num_views - 1 in views            # the padded last cluster
