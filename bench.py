@@ -657,7 +657,7 @@ def main():
         modes = {}
         for name, cs, rm in (("reuse_only", S, False), ("remap_only", 1, True), ("neither", 1, False)):
             b, _ = lfr.autotune(ctx, w.display, ds, cams, cluster_sizes=(cs,), reps=1, remap=rm,
-                                tiles=((16, 16), (32, 16), (32, 32), (32, 64), (64, 64)))
+                                tiles=((16, 16), (32, 16), (32, 32), (32, 64), (64, 64), (64, 128)))
             dm = lfr.Display(ctx, w.display.with_tile(b["tile_w"], b["tile_h"]))
             run = lambda: lfr.render(ctx, dm, ds, cams, cluster_size=cs, remap=rm, out=out)
             run()

@@ -60,7 +60,7 @@ typedef struct { int64_t num, den; } lfr_rational;
 /* Display description (section 3.1).  width/height in pixels (>= 1; three
  * subpixels per pixel), num_views N in [1, 65535], tan_slant = tan(alpha),
  * pitch = L_x in subpixels (> 0), offset = K_offset in subpixels, tile size
- * in pixels (tile_w, tile_h in {8, 16, 32, 64}).
+ * in pixels (tile_w, tile_h in {8, 16, 32, 64, 128}, tile_w * tile_h <= 8192).
  * The tile shape changes only the amount of work, never the image. */
 typedef struct {
     int32_t width, height, num_views;

@@ -1255,10 +1255,10 @@ static lfr_status display_finish(lfr_context *ctx, lfr_display *d, lfr_display *
     return LFR_OK;
 }
 
-// Tile sides 8..64 (powers of two), up to 64 x 64 pixels (the remap LUT
-// sorts a tile's subpixels in up to 64 KB of LDS).
-static bool tile_ok(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
-static bool tile_shape_ok(int tw, int th) { return tile_ok(tw) && tile_ok(th); }
+// Tile sides 8..128 (powers of two) with at most 8192 pixels per tile (the
+// remap LUT sorts a tile's subpixels in up to 128 KB of LDS).
+static bool tile_ok(int t) { return t == 8 || t == 16 || t == 32 || t == 64 || t == 128; }
+static bool tile_shape_ok(int tw, int th) { return tile_ok(tw) && tile_ok(th) && tw * th <= 8192; }
 
 static lfr_display *new_display(lfr_context *ctx, int W, int H, int N, int tw, int th)
 {
@@ -1290,7 +1290,7 @@ lfr_status lfr_display_create(lfr_context *ctx, const lfr_display_desc *desc, lf
     if (D.tan_slant.den <= 0 || D.pitch.den <= 0 || D.offset.den <= 0 || D.pitch.num <= 0)
         return fail(ctx, LFR_ERR_INVALID_ARG, "rational parameters need den > 0 and pitch > 0");
     if (!tile_shape_ok(D.tile_w, D.tile_h))
-        return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: sides must be 8, 16, 32 or 64",
+        return fail(ctx, LFR_ERR_INVALID_ARG, "tile %d x %d: sides must be 8, 16, 32, 64 or 128, area <= 8192",
                     D.tile_w, D.tile_h);
     if ((D.width + D.tile_w - 1) / D.tile_w > 65535 || (D.height + D.tile_h - 1) / D.tile_h > 65535)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
@@ -1339,7 +1339,7 @@ lfr_status lfr_display_create_from_map(lfr_context *ctx, int32_t W, int32_t H, i
     if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || N < 1 || N > 65535)
         return fail(ctx, LFR_ERR_INVALID_ARG, "bad panel or view count");
     if (!tile_shape_ok(tw, th))
-        return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16, 32 or 64");
+        return fail(ctx, LFR_ERR_INVALID_ARG, "tile sides must be 8, 16, 32, 64 or 128, area <= 8192");
     if ((W + tw - 1) / tw > 65535 || (H + th - 1) / th > 65535)
         return fail(ctx, LFR_ERR_UNSUPPORTED, "more than 65535 tiles per panel row or column");
     const size_t n = 3 * (size_t)W * H;

@@ -86,10 +86,11 @@ __device__ inline uint32_t tile_subpixel(const TileGeom &g, int W, int r)
 }
 
 // Psi for one tile: the tile's subpixels in row-major order (local rank r)
-// stably sorted by V.  Keys (V << 14) | r are unique (r < 3 * 64 * 64 <
-// 16384; V < 2^16, so keys stay below the all-ones padding), so a bitonic
-// sort in LDS yields exactly the stable order.  One 256-thread block per
-// tile; LDS holds next_pow2(3 * tw * th) keys (at most 16384, 64 KB).
+// stably sorted by V.  Keys (V << 15) | r are unique (r < 3 * 8192 < 32768;
+// V < 2^16, so keys stay below the all-ones padding), so a bitonic sort in
+// LDS yields exactly the stable order.  One 256-thread block per tile; LDS
+// holds next_pow2(3 * tw * th) keys (at most 32768, 128 KB of the CU's
+// 160 KB).
 __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, int H, int tw, int th,
                                                     uint32_t *psi)
 {
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, in
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
     for (int r = threadIdx.x; r < n2; r += blockDim.x)
-        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 14) | (uint32_t)r) : 0xFFFFFFFFu;
+        keys[r] = r < n ? (((uint32_t)V[tile_subpixel(g, W, r)] << 15) | (uint32_t)r) : 0xFFFFFFFFu;
     __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(256) remap_kernel(const uint16_t *V, int W, in
         }
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x)
-        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0x3FFFu));
+        psi[g.off + r] = tile_subpixel(g, W, (int)(keys[r] & 0x7FFFu));
 }
 
 hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_t *psi, hipStream_t s)
@@ -126,7 +127,14 @@ hipError_t launch_remap(const uint16_t *V, int W, int H, int tw, int th, uint32_
     const int T = ((W + tw - 1) / tw) * ((H + th - 1) / th);
     int n2 = 1;
     while (n2 < 3 * tw * th) n2 <<= 1;
-    hipLaunchKernelGGL(remap_kernel, dim3(T), dim3(256), (size_t)n2 * sizeof(uint32_t), s, V, W, H, tw, th, psi);
+    const size_t lds = (size_t)n2 * sizeof(uint32_t);
+    if (lds > 65536) {
+        // more than the default 64 KB of dynamic LDS per workgroup
+        const hipError_t e =
+            hipFuncSetAttribute((const void *)remap_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(remap_kernel, dim3(T), dim3(256), lds, s, V, W, H, tw, th, psi);
     return hipGetLastError();
 }
 

@@ -499,7 +499,7 @@ def render_fullframe_interlace(ctx: Context, display: Display, scene: DeviceScen
     return out
 
 
-DEFAULT_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64))
+DEFAULT_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64), (128, 64), (64, 128))
 
 
 def autotune(ctx: Context, params, scene: DeviceScene, cams, cluster_sizes=(8,), tiles=DEFAULT_TILES, reps=3,

@@ -87,6 +87,17 @@ def test_display_from_map_and_errors(lib):
     with pytest.raises(lfr.LfrError) as ei:
         lfr.Display(ctx, DisplayParams(33, 17, 5, Rational(1, 6), Rational(23, 5), tile_w=12, tile_h=8))
     assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    with pytest.raises(lfr.LfrError) as ei:                # 16384 pixels per tile: too many
+        lfr.Display(ctx, DisplayParams(33, 17, 5, Rational(1, 6), Rational(23, 5), tile_w=128, tile_h=128))
+    assert ei.value.code == lfr.LFR_ERR_INVALID_ARG
+    # the largest tiles (24576 subpixels each, sorted in 128 KB of LDS), with
+    # ragged edge tiles, against the oracle's remap table
+    for tw, th in ((128, 64), (64, 128)):
+        q = DisplayParams(300, 170, 7, Rational(1, 6), Rational(23, 5), tile_w=tw, tile_h=th)
+        Vq = oracle.view_map(q)
+        dq = lfr.Display(ctx, view_map=Vq, width=300, height=170, num_views=7, tile=(tw, th))
+        np.testing.assert_array_equal(dq.remap(), oracle.remap(q, Vq))
+        dq.close()
 
 
 # --------------------------------------------------------------------------
@@ -348,7 +359,7 @@ def test_work_counts_agree_across_blend_orders(lib, tiny_setup, S, first_chunk):
     d.close()
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64), (64, 64)])
+@pytest.mark.parametrize("tile", [(8, 8), (32, 32), (16, 8), (64, 32), (32, 64), (64, 64), (128, 64), (64, 128)])
 def test_tiling_does_not_change_the_image(lib, tiny_setup, tile):
     lfr, ctx = lib
     w, scene, cams, V, ds = tiny_setup
@@ -530,8 +541,8 @@ def test_display_workload_tilings_and_chunks_agree(lib):
     the alive tables between chunks) on three tilings that take different
     code paths: 8x8 tiles (135 tile rows, a 136 x 241 summed-area table:
     no row/column masks, the table built outside LDS), 32x32, 32x64 and 64x64
-    (masks and the LDS table; 64x64 tiles of 12288 subpixels, the remap
-    table's largest sort).  Coverage is conservative, so every rendering must be
+    (masks and the LDS table) and 64x128 (24576 subpixels per tile, the remap
+    table's largest sort, in 128 KB of LDS).  Coverage is conservative, so every rendering must be
     bit-identical, and equal to one chunk from a single full depth sort."""
     lfr, ctx = lib
     w = get_workload("display")
@@ -539,7 +550,7 @@ def test_display_workload_tilings_and_chunks_agree(lib):
     cams = pack_cameras(w.cameras())
     ds = lfr.DeviceScene.from_numpy(scene)
     ref = None
-    for tile in ((32, 32), (8, 8), (32, 64), (64, 64)):
+    for tile in ((32, 32), (8, 8), (32, 64), (64, 128)):
         d = _display(lfr, ctx, w.display.with_tile(*tile))
         for S, fc in ((4, 2048), (4, 1 << 20), (1, 4096)):
             img = _render(lfr, ctx, d, ds, cams, cluster_size=S, first_chunk=fc)
@@ -557,7 +568,7 @@ def test_display_workload_tilings_and_chunks_agree(lib):
 
 
 # the tile shapes the benchmark's autotuner chooses among
-BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64))
+BENCH_TILES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64), (128, 64), (64, 128))
 
 
 @pytest.fixture(scope="module")
@@ -612,7 +623,7 @@ def test_paper_display_shapes(lib, outdoor, name, S):
     """The paper's two display shapes (71 views over 53 degrees at 3840x2160
     with reuse groups of 18; 63 views over 53 degrees at 1440x2560 with groups
     of 16, the last group padded) on the 3M-Gaussian scene, on the tile shapes
-    the benchmark picks among (64x32, 32x64 and 64x64, bit-identical): subpixels spread
+    the benchmark picks among (64x32, 32x64, 64x64, 128x64, 64x128; bit-identical): subpixels spread
     over every view against the oracle, and the exact path's image against
     full-frame-then-interlace on the same display."""
     lfr, ctx = lib
@@ -624,7 +635,7 @@ def test_paper_display_shapes(lib, outdoor, name, S):
     assert len(np.unique(V)) == w.display.num_views
     ds = lfr.DeviceScene.from_numpy(scene)
     imgs = {}
-    for tile in ((64, 32), (32, 64), (64, 64)):
+    for tile in ((64, 32), (32, 64), (64, 64), (128, 64), (64, 128)):
         d = _display(lfr, ctx, w.display.with_tile(*tile))
         imgs[tile] = _render(lfr, ctx, d, ds, cams, cluster_size=S)
         say(" tile", tile, ctx.stats()["pairs"], "pairs")
@@ -635,7 +646,8 @@ def test_paper_display_shapes(lib, outdoor, name, S):
             np.testing.assert_array_equal(ff.cpu().numpy(), exact)
         d.close()
     np.testing.assert_array_equal(imgs[(64, 32)], imgs[(32, 64)])
-    np.testing.assert_array_equal(imgs[(64, 32)], imgs[(64, 64)])
+    for tile in ((64, 64), (128, 64), (64, 128)):
+        np.testing.assert_array_equal(imgs[(64, 32)], imgs[tile], err_msg=f"tile {tile}")
     img = imgs[(64, 32)]
     samples, views = _sample_every_view(V, 2048, 3)
     assert w.display.num_views - 1 in views            # the padded last cluster
