@@ -182,7 +182,7 @@ def test_full_size_serving_batch_against_oracle(lib, S):
     """The serving configuration at full size: three outdoor-style scenes
     (0.5M / 1M / 3M Gaussians) on 1920x1080/45-view, 2560x1440/64-view and
     3840x2160/100-view panels, two head poses each, on the tiles the
-    benchmark's autotuner picks for them (32x64, 32x64 and 64x64), rendered
+    benchmark's autotuner picks for them (32x64, 32x64 and 64x128), rendered
     by lfr_render_batch (planned, replayed from captured graphs).  Every
     frame equals lfr_render's image; one frame of each panel is checked
     against the oracle on about 1024 subpixels spread over all its views."""
@@ -194,7 +194,7 @@ def test_full_size_serving_batch_against_oracle(lib, S):
         say("panel", disp.width, disp.height, disp.num_views, "scene", seed_i, m)
         sc = mixture_scene(seed_i, m, 3)
         ds = lfr.DeviceScene.from_numpy(sc, device="cuda:0")
-        d = lfr.Display(ctx, disp.with_tile(*((64, 64) if disp.width >= 3840 else (32, 64))))
+        d = lfr.Display(ctx, disp.with_tile(*((64, 128) if disp.width >= 3840 else (32, 64))))
         keep.append((d, ds, sc, disp, radius, span))
         for o in offs:
             cams = pack_cameras(orbit_rig(disp.num_views, disp.width, disp.height, radius, span, 60.0,
