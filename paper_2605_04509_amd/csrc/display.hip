@@ -156,35 +156,49 @@ __global__ void __launch_bounds__(64) task_kernel(const uint16_t *V, const uint3
     int cur = -2, cnt = 0, nviews = 0, last_v = -1;
     Task tk{};
     Task *out = kEmit ? tasks + offsets[t] : nullptr;
-    for (int r = 0; r < n; ++r) {
-        const int v = V[psi[g.off + r]];
-        const int c = view_cluster[v];
-        if (c < 0) continue;
-        const bool new_view = v != last_v;
-        if (c != cur || cnt == kWave || (new_view && nviews == kMaxWaveViews)) {
-            if (kEmit && cur >= 0) out[nt - 1] = tk;
-            ++nt;
-            cur = c;
-            cnt = 0;
-            nviews = 0;
-            last_v = -1;
-            tk = Task{};
-            tk.tile = (uint32_t)t;
-            tk.cluster = (uint32_t)c;
-            tk.start = (uint32_t)(g.off + r);
-            for (int q = 0; q < 4; ++q) tk.run_start[q] = (uint8_t)kWave;
-        }
-        if (v != last_v) {
-            if (kEmit) {
-                tk.run_start[nviews] = (uint8_t)cnt;
-                tk.slot[nviews] = (uint16_t)view_slot[v];
+    // 16 subpixels at a time: their Psi entries, views and clusters are each
+    // loaded together, then walked one by one in order
+    constexpr int kStep = 16;
+    for (int r0 = 0; r0 < n; r0 += kStep) {
+        int vs[kStep], cs[kStep];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) vs[q] = (int)psi[g.off + min(r0 + q, n - 1)];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) vs[q] = V[vs[q]];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) cs[q] = view_cluster[vs[q]];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) {
+            const int r = r0 + q;
+            if (r >= n) break;
+            const int v = vs[q], c = cs[q];
+            if (c < 0) continue;
+            const bool new_view = v != last_v;
+            if (c != cur || cnt == kWave || (new_view && nviews == kMaxWaveViews)) {
+                if (kEmit && cur >= 0) out[nt - 1] = tk;
+                ++nt;
+                cur = c;
+                cnt = 0;
+                nviews = 0;
+                last_v = -1;
+                tk = Task{};
+                tk.tile = (uint32_t)t;
+                tk.cluster = (uint32_t)c;
+                tk.start = (uint32_t)(g.off + r);
+                for (int e = 0; e < 4; ++e) tk.run_start[e] = (uint8_t)kWave;
             }
-            ++nviews;
-            last_v = v;
+            if (v != last_v) {
+                if (kEmit) {
+                    tk.run_start[nviews] = (uint8_t)cnt;
+                    tk.slot[nviews] = (uint16_t)view_slot[v];
+                }
+                ++nviews;
+                last_v = v;
+            }
+            ++cnt;
+            tk.count = (uint16_t)cnt;
+            tk.n_runs = (uint16_t)nviews;
         }
-        ++cnt;
-        tk.count = (uint16_t)cnt;
-        tk.n_runs = (uint16_t)nviews;
     }
     if (kEmit) {
         if (cur >= 0) out[nt - 1] = tk;
