@@ -28,7 +28,8 @@ if ROOT not in sys.path:
 METRIC = "interlaced LF frames/s (4K, 100 views) reuse+remap vs plain; fwd+bwd ms"
 # VALU issue roof: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-operations/s
 # (one vector instruction slot per lane per clock, FMA counted once; packed
-# FP32 is not used by this build, so it is the roof of the plain ALU path)
+# FP32 is not used by the library (it is compiled with packed FP32 off), so
+# this is the roof of its plain ALU path)
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 OPS_PER_EVAL = 14        # alpha per (subpixel, Gaussian): dx, dy (2) + w = dx + beta dy (1) + w^2, dy^2 (2)
